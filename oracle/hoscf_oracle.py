@@ -1,0 +1,472 @@
+"""FP64 reference implementation of the HOSCF / iHOSCF hot path.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): nothing in the product
+path may import this module.
+
+Notation follows the paper: T is the order-N tensor (the paper's A, order d),
+x_n are the unit factor vectors (u^(n)), sigma is the objective / singular
+value (lambda), and the stacked unit vector x~ = [x_1; ...; x_N] / sqrt(N).
+
+Readings of passages where the paper is silent or garbled (each also listed in
+the design doc):
+  * J is always built at the latest normalised iterate (Alg. 1 indexing).
+  * The stopping test of eq. (stop-3) is the NEPv residual at the iterate with
+    J rebuilt there: ||J(x~)x~ - rho x~|| / (||J||_F + |sigma|), rho = sigma.
+  * Largest-magnitude ties prefer the positive eigenvalue.
+  * Signs are canonicalised every iteration: for n >= 2 the largest-|entry| of
+    x_n is made positive (lowest index on ties), flipping x_1 with it; at the
+    end sigma >= 0 by flipping x_1 (Alg. 1, final sign fix).
+  * A zero block in the eigenvector (eq. factor) stops with DEGENERATE.
+  * The iHOSCF Rayleigh step uses J rebuilt at the new iterate,
+    z = (J - rho I)^{-1} x~, and is accepted iff |z'Jz| / z'z > |rho|; a
+    singular shifted matrix rejects the step.
+
+Inputs are whatever the caller stored (FP64, FP32, BF16/FP8 already
+dequantised by the caller); every arithmetic step here runs in FP64.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Degenerate", "OK", "NOT_CONVERGED", "DEGENERATE",
+    "split", "stack", "ttvc", "outer", "objective", "mode_vectors", "blocks",
+    "j_matrix", "residual", "top_magnitude_eigpair", "normalize_blocks",
+    "canonical_signs", "sweep", "hoscf", "hopm", "greedy_deflation",
+    "grad_solve", "grad_ttvc", "Result", "angle", "fd_directional", "rqi_step", "Sweep",
+]
+
+OK, NOT_CONVERGED, DEGENERATE = 0, 1, -4
+
+# Mode-1 slab size (in entries of the remaining modes) used when upcasting a
+# stored tensor to FP64 piece by piece.
+_SLAB_ENTRIES = 1 << 24
+
+
+class Degenerate(Exception):
+    """A factor block of the eigenvector is exactly zero (eq. factor sets the
+    factor to 0 there); the iteration cannot continue."""
+
+
+# ---------------------------------------------------------------------------
+# Basic operations (Section 2)
+# ---------------------------------------------------------------------------
+
+def split(x: np.ndarray, dims: Sequence[int]) -> List[np.ndarray]:
+    """Blocks x_{index_n} of a stacked vector (eq. factor: index_n are
+    consecutive ranges of lengths I_1, ..., I_N)."""
+    out, off = [], 0
+    for d in dims:
+        out.append(np.asarray(x[off:off + d], dtype=np.float64))
+        off += d
+    return out
+
+
+def stack(xs: Sequence[np.ndarray]) -> np.ndarray:
+    return np.concatenate([np.asarray(v, dtype=np.float64) for v in xs])
+
+
+def ttvc(X: np.ndarray, vecs: Dict[int, np.ndarray]) -> np.ndarray:
+    """Tensor-times-vector chain (Section 2): contract mode k of X with
+    vecs[k] for every key k.  Modes are contracted from the highest position
+    down so that the remaining positions keep their meaning."""
+    for k in sorted(vecs, reverse=True):
+        X = np.tensordot(X, vecs[k], axes=([k], [0]))
+    return X
+
+
+def outer(vecs: Sequence[np.ndarray]) -> np.ndarray:
+    """Rank-one tensor u1 o u2 o ... o uN (eq. rank-one)."""
+    out = np.asarray(vecs[0], dtype=np.float64)
+    for v in vecs[1:]:
+        out = np.multiply.outer(out, np.asarray(v, dtype=np.float64))
+    return out
+
+
+def _slabs(T: np.ndarray):
+    """Yield (start, stop, FP64 copy of T[start:stop]) along mode 1."""
+    I1 = T.shape[0]
+    rest = max(1, T.size // max(I1, 1))
+    step = max(1, _SLAB_ENTRIES // rest)
+    for s in range(0, I1, step):
+        e = min(I1, s + step)
+        yield s, e, np.asarray(T[s:e], dtype=np.float64)
+
+
+def objective(T: np.ndarray, xs: Sequence[np.ndarray]) -> float:
+    """T x_1 u1 x_2 u2 ... x_N uN (eq. rank-one approx-2), full contraction."""
+    N = T.ndim
+    total = 0.0
+    for s, e, S in _slabs(T):
+        vec = {0: xs[0][s:e]}
+        vec.update({k: xs[k] for k in range(1, N)})
+        total += float(ttvc(S, vec))
+    return total
+
+
+def mode_vectors(T: np.ndarray, xs: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """g_n = T x_{k != n} u_k for every n (left-hand sides of eq. kkt).  Each
+    is its own contraction chain over T, independent of the J blocks."""
+    N = T.ndim
+    g = [np.zeros(T.shape[n]) for n in range(N)]
+    for s, e, S in _slabs(T):
+        for n in range(N):
+            vec = {k: xs[k] for k in range(1, N) if k != n}
+            if n == 0:
+                g[0][s:e] = ttvc(S, vec)
+            else:
+                vec[0] = xs[0][s:e]
+                g[n] += ttvc(S, vec)
+    return g
+
+
+def blocks(T: np.ndarray, xs: Sequence[np.ndarray]) -> Dict[Tuple[int, int], np.ndarray]:
+    """Every off-diagonal block A_{m,n}(x), m < n (eq. submatrix): T
+    contracted with u_k on all modes k not in {m, n}; an I_m x I_n matrix.
+    Each block is a separate contraction chain over T, in FP64 slabs."""
+    N = T.ndim
+    out = {(m, n): np.zeros((T.shape[m], T.shape[n]))
+           for m in range(N) for n in range(m + 1, N)}
+    for s, e, S in _slabs(T):
+        for (m, n), A in out.items():
+            others = [k for k in range(N) if k not in (m, n)]
+            vec = {k: xs[k] for k in others if k != 0}
+            if m == 0:
+                A[s:e] = ttvc(S, vec)
+            else:
+                vec[0] = xs[0][s:e]
+                A += ttvc(S, vec)
+    return out
+
+
+def j_matrix(blk: Dict[Tuple[int, int], np.ndarray], dims: Sequence[int]) -> np.ndarray:
+    """The symmetric matrix J(x) of eq. (map): zero diagonal blocks, block
+    (m, n) = A_{m,n}, block (n, m) = A_{m,n}^T, all scaled by 1/(N-1)."""
+    N = len(dims)
+    off = np.concatenate([[0], np.cumsum(dims)])
+    D = int(off[-1])
+    J = np.zeros((D, D))
+    for (m, n), A in blk.items():
+        J[off[m]:off[m + 1], off[n]:off[n + 1]] = A
+        J[off[n]:off[n + 1], off[m]:off[m + 1]] = A.T
+    return J / (N - 1)
+
+
+def residual(g: Sequence[np.ndarray], xs: Sequence[np.ndarray], sigma: float,
+             blk: Dict[Tuple[int, int], np.ndarray]) -> Tuple[float, float]:
+    """Residual of eq. (stop-3) at the iterate, under the reading that J is
+    rebuilt there.  Because A_{n,m} u_m = g_n for every m != n,
+    J(x~)x~ = [g_n]/sqrt(N) and rho = x~'J(x~)x~ = sigma, so the numerator is
+    sqrt(sum_n ||g_n - sigma u_n||^2 / N).  Returns (res, ||J||_F)."""
+    N = len(xs)
+    num = math.sqrt(sum(float(np.sum((g[n] - sigma * xs[n]) ** 2)) for n in range(N)) / N)
+    fro2 = sum(float(np.sum(A * A)) for A in blk.values())
+    normJ = math.sqrt(2.0 * fro2) / (N - 1)
+    den = normJ + abs(sigma)
+    return (num / den if den > 0 else math.inf), normJ
+
+
+def top_magnitude_eigpair(J: np.ndarray, tie_rtol: float = 1e-12) -> Tuple[float, np.ndarray]:
+    """Largest-magnitude eigenpair of the symmetric J (Alg. 1, eigen-step),
+    from dense LAPACK eigh.  If the most negative eigenvalue is not larger in
+    magnitude than the most positive one by more than a relative 1e-12, the
+    positive one is taken."""
+    w, V = np.linalg.eigh(J)
+    lo, hi = w[0], w[-1]
+    if abs(lo) > abs(hi) * (1.0 + tie_rtol):
+        return float(lo), V[:, 0].copy()
+    return float(hi), V[:, -1].copy()
+
+
+def normalize_blocks(y: np.ndarray, dims: Sequence[int]) -> List[np.ndarray]:
+    """u_n = y_{index_n} / ||y_{index_n}|| (eq. factor and the normalisation
+    lines of Alg. 1).  A zero block raises Degenerate."""
+    xs = []
+    for v in split(y, dims):
+        nrm = math.sqrt(float(np.dot(v, v)))
+        if nrm == 0.0:
+            raise Degenerate("zero factor block")
+        xs.append(v / nrm)
+    return xs
+
+
+def canonical_signs(xs: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Fix the sign representative: for n >= 2 the largest-|entry| of u_n
+    (lowest index on ties) is made positive, and u_1 is flipped along with it.
+    The map x_n -> s_n x_n with prod s_n = 1 leaves T(u) and the iteration
+    unchanged (Theorem 1, P1, generalised to any block), so this only selects
+    the representative."""
+    xs = [np.array(v, dtype=np.float64, copy=True) for v in xs]
+    for n in range(1, len(xs)):
+        i = int(np.argmax(np.abs(xs[n])))
+        if xs[n][i] < 0:
+            xs[n] = -xs[n]
+            xs[0] = -xs[0]
+    return xs
+
+
+# ---------------------------------------------------------------------------
+# One sweep: everything the TTVc J-build produces at an iterate
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Sweep:
+    blocks: Dict[Tuple[int, int], np.ndarray]
+    g: List[np.ndarray]
+    sigma: float
+    res: float
+    normJ: float
+
+
+def sweep(T: np.ndarray, xs: Sequence[np.ndarray]) -> Sweep:
+    """Blocks A_{m,n}, mode vectors, sigma = u_1'g_1 and the residual at xs.
+    Mode vectors come from the blocks (g_1 = A_{1,2}u_2, g_n = A_{1,n}'u_1)."""
+    blk = blocks(T, xs)
+    N = T.ndim
+    g = [blk[(0, 1)] @ xs[1]] + [blk[(0, n)].T @ xs[0] for n in range(1, N)]
+    sigma = float(xs[0] @ g[0])
+    res, normJ = residual(g, xs, sigma, blk)
+    return Sweep(blk, g, sigma, res, normJ)
+
+
+def rqi_step(J: np.ndarray, xt: np.ndarray) -> Optional[np.ndarray]:
+    """One Rayleigh quotient iteration step (Section 4.4): rho = x'Jx / x'x,
+    z = (J - rho I)^{-1} x, z <- z / ||z||.  Returns z when its Rayleigh
+    quotient is larger in magnitude than rho (the acceptance rule), None when
+    it is not or when J - rho I is singular."""
+    rho = float(xt @ J @ xt) / float(xt @ xt)
+    try:
+        z = np.linalg.solve(J - rho * np.eye(J.shape[0]), xt)
+    except np.linalg.LinAlgError:
+        return None
+    nz = float(np.linalg.norm(z))
+    if not np.isfinite(nz) or nz == 0.0:
+        return None
+    z = z / nz
+    if abs(float(z @ J @ z)) > abs(rho):
+        return z
+    return None
+
+
+# ---------------------------------------------------------------------------
+# HOSCF and iHOSCF (Section 4, Alg. 1 and the improved variant)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    sigma: float
+    xs: List[np.ndarray]
+    status: int
+    iters: int
+    sweeps: int
+    residual: float
+    rqi_accepted: int = 0
+    lambda0: float = 0.0
+    history: List[float] = field(default_factory=list)
+
+    @property
+    def x(self) -> np.ndarray:
+        return stack(self.xs)
+
+
+def hoscf(T: np.ndarray, x0, algo: str = "hoscf", tol: float = 1e-10,
+          max_iter: int = 500, canonical: bool = True) -> Result:
+    """HOSCF (Alg. 1) or iHOSCF (Section 4.4), FP64.
+
+    Loop: build J at the current iterate (one sweep), test the residual,
+    take the largest-magnitude eigenpair of J, normalise its blocks, fix
+    signs.  iHOSCF then rebuilds J at the new iterate, forms the Rayleigh
+    quotient rho, solves (J - rho I) z = x~ and keeps z (block-normalised)
+    only if its Rayleigh quotient exceeds |rho| in magnitude.  When the step
+    is rejected, the J already built at the iterate is reused for the next
+    residual test.  At the end sigma = T(u) directly, made >= 0 by flipping
+    u_1 (Alg. 1, final lines)."""
+    dims = list(T.shape)
+    N = len(dims)
+    if algo not in ("hoscf", "ihoscf"):
+        raise ValueError(algo)
+    xs = normalize_blocks(stack(x0) if not isinstance(x0, np.ndarray) else x0, dims)
+    lam0 = objective(T, xs)
+    sw = sweep(T, xs)
+    sweeps, iters, accepted = 1, 0, 0
+    hist = [sw.res]
+    status = NOT_CONVERGED
+    while True:
+        if sw.res <= tol:
+            status = OK
+            break
+        if iters >= max_iter:
+            break
+        J = j_matrix(sw.blocks, dims)
+        _, y = top_magnitude_eigpair(J)
+        try:
+            xs = normalize_blocks(y, dims)
+        except Degenerate:
+            status = DEGENERATE
+            break
+        if canonical:
+            xs = canonical_signs(xs)
+        iters += 1
+        sw = sweep(T, xs)
+        sweeps += 1
+        if algo == "ihoscf":
+            J = j_matrix(sw.blocks, dims)
+            z = rqi_step(J, stack(xs) / math.sqrt(N))
+            if z is not None:
+                try:
+                    xz = normalize_blocks(z, dims)
+                except Degenerate:
+                    xz = None
+                if xz is not None:
+                    xs = canonical_signs(xz) if canonical else xz
+                    sw = sweep(T, xs)
+                    sweeps += 1
+                    accepted += 1
+        hist.append(sw.res)
+    sigma = objective(T, xs)
+    if sigma < 0:
+        sigma = -sigma
+        xs = [-xs[0]] + [v.copy() for v in xs[1:]]
+    return Result(sigma, xs, status, iters, sweeps, sw.res, accepted, lam0, hist)
+
+
+# ---------------------------------------------------------------------------
+# HOPM (Gauss-Seidel baseline named in Section 1)
+# ---------------------------------------------------------------------------
+
+def hopm(T: np.ndarray, x0, tol: float = 1e-12, max_iter: int = 1000) -> Result:
+    """Higher-order power method: u_n <- normalise(T x_{k != n} u_k), one
+    mode after another with the newest factors.  Stops when sigma changes by
+    at most tol relative.  Signs canonicalised and sigma >= 0 at the end."""
+    dims = list(T.shape)
+    N = len(dims)
+    xs = normalize_blocks(stack(x0) if not isinstance(x0, np.ndarray) else x0, dims)
+    prev = objective(T, xs)
+    status, it = NOT_CONVERGED, 0
+    for it in range(1, max_iter + 1):
+        for n in range(N):
+            vec = {k: xs[k] for k in range(N) if k != n}
+            v = ttvc(np.asarray(T, dtype=np.float64), vec)
+            nrm = np.linalg.norm(v)
+            if nrm == 0:
+                return Result(prev, xs, DEGENERATE, it, it, math.inf)
+            xs[n] = v / nrm
+        cur = objective(T, xs)
+        if abs(cur - prev) <= tol * abs(cur):
+            prev = cur
+            status = OK
+            break
+        prev = cur
+    xs = canonical_signs(xs)
+    sigma = objective(T, xs)
+    if sigma < 0:
+        sigma, xs[0] = -sigma, -xs[0]
+    return Result(sigma, xs, status, it, it, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Greedy rank-one update (deflation), Section 1 and Example 3
+# ---------------------------------------------------------------------------
+
+def greedy_deflation(T: np.ndarray, x0s: Sequence, rank: int, algo: str = "hoscf",
+                     tol: float = 1e-10, max_iter: int = 500):
+    """A^(1) = T; B^(r) = best rank-one of A^(r) (by HOSCF from x0s[r]);
+    A^(r+1) = A^(r) - B^(r), subtracted explicitly in FP64.  Returns the
+    per-term results and res_r = ||A^(r+1)||_F / ||A^(1)||_F."""
+    A = np.asarray(T, dtype=np.float64).copy()
+    norm0 = float(np.linalg.norm(A))
+    results, res = [], []
+    for r in range(rank):
+        out = hoscf(A, x0s[r], algo=algo, tol=tol, max_iter=max_iter)
+        results.append(out)
+        A = A - out.sigma * outer(out.xs)
+        res.append(float(np.linalg.norm(A)) / norm0 if norm0 > 0 else 0.0)
+    return results, res
+
+
+# ---------------------------------------------------------------------------
+# Derivatives (project addition: differentiation of the solve and the sweep)
+# ---------------------------------------------------------------------------
+
+def grad_solve(T: np.ndarray, xs: Sequence[np.ndarray], sigma: float, g_sigma: float,
+               g_x: Optional[Sequence[np.ndarray]] = None):
+    """Gradient of L(sigma, u) w.r.t. T at a KKT point (eq. kkt).
+
+    Linearising T x_{k!=n} u_k = sigma u_n, ||u_n|| = 1 gives, with
+    M = (N-1) J(x) and X = blockdiag(u_n), the symmetric bordered system
+        [[M - sigma I, X], [X', 0]] [mu; nu] = [g_x; 0]
+    and dL/dT = g_sigma * (u_1 o ... o u_N) - sum_n u_1 o .. o mu_n o .. o u_N
+    (d sigma / dT = u_1 o ... o u_N by the envelope theorem).  Dense FP64
+    solve.  Returns (dT, mu as a list of blocks)."""
+    dims = list(T.shape)
+    N = len(dims)
+    D = sum(dims)
+    blk = blocks(T, xs)
+    M = j_matrix(blk, dims) * (N - 1)
+    X = np.zeros((D, N))
+    off = 0
+    for n, d in enumerate(dims):
+        X[off:off + d, n] = xs[n]
+        off += d
+    K = np.zeros((D + N, D + N))
+    K[:D, :D] = M - sigma * np.eye(D)
+    K[:D, D:] = X
+    K[D:, :D] = X.T
+    rhs = np.zeros(D + N)
+    if g_x is not None:
+        rhs[:D] = stack(g_x)
+    sol = np.linalg.solve(K, rhs)
+    mu = split(sol[:D], dims)
+    dT = g_sigma * outer(xs)
+    for n in range(N):
+        vecs = list(xs)
+        vecs[n] = mu[n]
+        dT = dT - outer(vecs)
+    return dT, mu
+
+
+def grad_ttvc(T: np.ndarray, xs: Sequence[np.ndarray], gbar: Sequence[np.ndarray],
+              sigma_bar: float):
+    """Adjoint of one sweep's differentiable outputs g_n = T x_{k!=n} u_k and
+    sigma = T(u), for cotangents gbar_n and sigma_bar:
+        dT   = sum_n u_1 o .. o gbar_n o .. o u_N + sigma_bar * u_1 o .. o u_N
+        dx_m = sum_{n != m} A_{m,n} gbar_n + sigma_bar * g_m
+    where A_{m,n} is oriented I_m x I_n (A_{n,m} = A_{m,n}')."""
+    N = T.ndim
+    blk = blocks(T, xs)
+    g = mode_vectors(T, xs)
+    dT = sigma_bar * outer(xs)
+    for n in range(N):
+        vecs = list(xs)
+        vecs[n] = np.asarray(gbar[n], dtype=np.float64)
+        dT = dT + outer(vecs)
+    dx = []
+    for m in range(N):
+        acc = sigma_bar * g[m]
+        for n in range(N):
+            if n == m:
+                continue
+            A = blk[(m, n)] if m < n else blk[(n, m)].T
+            acc = acc + A @ np.asarray(gbar[n], dtype=np.float64)
+        dx.append(acc)
+    return dT, dx
+
+
+def angle(u: np.ndarray, v: np.ndarray) -> float:
+    """Angle between the lines spanned by u and v (sign-free), robust near 0."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    v = v / np.linalg.norm(v)
+    if float(u @ v) < 0:
+        v = -v
+    return 2.0 * math.atan2(float(np.linalg.norm(u - v)), float(np.linalg.norm(u + v)))
+
+
+def fd_directional(loss, T: np.ndarray, E: np.ndarray, h: float = 1e-6) -> float:
+    """Central finite difference (loss(T + hE) - loss(T - hE)) / 2h."""
+    return (loss(T + h * E) - loss(T - h * E)) / (2.0 * h)

@@ -1,0 +1,484 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None re-types the oracle's formula:
+they use brute force on tiny inputs, closed forms (planted rank-one, the
+matrix case, orthogonally decomposable tensors), printed values (Example 2),
+invariants (eq. kkt, Theorem 1 P2, Theorem 3) and finite differences.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_01778_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_tensor(dims, seed):
+    return np.random.default_rng(seed).standard_normal(dims)
+
+
+def rand_unit(dims, seed):
+    rng = np.random.default_rng(seed)
+    return [v / np.linalg.norm(v) for v in (rng.standard_normal(d) for d in dims)]
+
+
+# ---------------------------------------------------------------------------
+# eq. (submatrix), the TTVc, mode vectors and sigma by explicit loops
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(3, 4, 5), (2, 3, 2, 3), (2, 2, 3, 1, 2)])
+def test_blocks_match_elementwise_definition(dims):
+    T = rand_tensor(dims, 11)
+    xs = rand_unit(dims, 12)
+    N = len(dims)
+    blk = oracle.blocks(T, xs)
+    g = oracle.mode_vectors(T, xs)
+    sig = oracle.objective(T, xs)
+    ref_blk = {(m, n): np.zeros((dims[m], dims[n])) for m in range(N) for n in range(m + 1, N)}
+    ref_g = [np.zeros(d) for d in dims]
+    ref_sig = 0.0
+    for idx in itertools.product(*[range(d) for d in dims]):
+        t = T[idx]
+        prod_all = t
+        for k in range(N):
+            prod_all *= xs[k][idx[k]]
+        ref_sig += prod_all
+        for n in range(N):
+            p = t
+            for k in range(N):
+                if k != n:
+                    p *= xs[k][idx[k]]
+            ref_g[n][idx[n]] += p
+        for (m, n) in ref_blk:
+            p = t
+            for k in range(N):
+                if k not in (m, n):
+                    p *= xs[k][idx[k]]
+            ref_blk[(m, n)][idx[m], idx[n]] += p
+    for key in ref_blk:
+        np.testing.assert_allclose(blk[key], ref_blk[key], rtol=1e-12, atol=1e-12)
+    for n in range(N):
+        np.testing.assert_allclose(g[n], ref_g[n], rtol=1e-12, atol=1e-12)
+    assert sig == pytest.approx(ref_sig, rel=1e-12, abs=1e-12)
+
+
+def test_slabbed_upcast_equals_whole(monkeypatch):
+    """Processing T in mode-1 slabs gives the same blocks as one slab."""
+    dims = (9, 5, 4, 3)
+    T = rand_tensor(dims, 3).astype(np.float32)
+    xs = rand_unit(dims, 4)
+    whole = oracle.blocks(T, xs)
+    import oracle.hoscf_oracle as ho
+    monkeypatch.setattr(ho, "_SLAB_ENTRIES", 7)
+    sl = oracle.blocks(T, xs)
+    for k in whole:
+        np.testing.assert_allclose(sl[k], whole[k], rtol=1e-13, atol=1e-13)
+
+
+def test_j_matrix_structure_and_identity():
+    """eq. (map): J symmetric with zero diagonal blocks; with u_n unit,
+    J(x~)x~ = [T x_{k!=n} u_k]_n / sqrt(N) and x~'Jx~ = T(u)."""
+    dims = (4, 3, 5, 2)
+    T = rand_tensor(dims, 5)
+    xs = rand_unit(dims, 6)
+    J = oracle.j_matrix(oracle.blocks(T, xs), dims)
+    np.testing.assert_allclose(J, J.T, atol=0)
+    off = np.concatenate([[0], np.cumsum(dims)])
+    for n in range(len(dims)):
+        assert np.all(J[off[n]:off[n + 1], off[n]:off[n + 1]] == 0)
+    xt = oracle.stack(xs) / math.sqrt(len(dims))
+    g = oracle.mode_vectors(T, xs)
+    np.testing.assert_allclose(J @ xt, oracle.stack(g) / math.sqrt(len(dims)), rtol=1e-12, atol=1e-13)
+    assert float(xt @ J @ xt) == pytest.approx(oracle.objective(T, xs), rel=1e-12)
+
+
+def test_residual_equals_dense_stop3():
+    """eq. (stop-3) evaluated with the dense J at the iterate."""
+    dims = (5, 4, 3)
+    T = rand_tensor(dims, 7)
+    xs = rand_unit(dims, 8)
+    sw = oracle.sweep(T, xs)
+    J = oracle.j_matrix(sw.blocks, dims)
+    xt = oracle.stack(xs) / math.sqrt(3)
+    rho = float(xt @ J @ xt)
+    dense = np.linalg.norm(J @ xt - rho * xt) / (np.linalg.norm(J, "fro") + abs(rho))
+    assert sw.res == pytest.approx(dense, rel=1e-12)
+    assert sw.normJ == pytest.approx(np.linalg.norm(J, "fro"), rel=1e-12)
+    assert sw.sigma == pytest.approx(rho, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P1 planted rank-one, P2 matrix case
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(6, 5, 4), (4, 3, 5, 2), (3, 3, 3, 3, 3)])
+def test_planted_noise_free_exact(dims):
+    """Section 2 (rank-one tensors) with Theorem 2: T = lam a o b o ...
+    gives sigma = lam and the planted factors after one eigen-step."""
+    lam = 7.25
+    T, fac = synth.planted_rank_one(dims, lam, 21, dtype=np.float64, noise_std=0.0)
+    x0 = synth.init_factors(dims, 22)
+    r = oracle.hoscf(T, x0, tol=1e-13, max_iter=5)
+    assert r.status == oracle.OK
+    assert r.iters <= 1
+    assert r.sigma == pytest.approx(lam, rel=1e-13)
+    for a, x in zip(fac, r.xs):
+        assert oracle.angle(a, x) < 1e-7
+    rebuilt = r.sigma * oracle.outer(r.xs)
+    np.testing.assert_allclose(rebuilt, T, atol=1e-12 * lam)
+
+
+def test_matrix_case_is_svd():
+    """Section 3, d = 2: J is constant and the largest eigenpair is the
+    largest singular pair (Eckart-Young-Mirsky)."""
+    A = rand_tensor((7, 5), 31)
+    U, s, Vt = np.linalg.svd(A)
+    r = oracle.hoscf(A, synth.init_factors(A.shape, 32), tol=1e-13, max_iter=3)
+    assert r.status == oracle.OK and r.iters <= 1
+    assert r.sigma == pytest.approx(s[0], rel=1e-13)
+    assert oracle.angle(r.xs[0], U[:, 0]) < 1e-7
+    assert oracle.angle(r.xs[1], Vt[0]) < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# P3 KKT, P4 equal block norms, P5 eigenvalue of J(x*), P12 bounds
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def converged_small():
+    T, fac = synth.planted_rank_one((8, 7, 6), 6.0, 41, dtype=np.float64)
+    r = oracle.hoscf(T, synth.init_factors(T.shape, 41), tol=1e-13, max_iter=2000)
+    assert r.status == oracle.OK
+    return T, fac, r
+
+
+def test_kkt_at_convergence(converged_small):
+    """eq. (kkt): T x_{k!=n} u_k = sigma u_n, from an independent chain."""
+    T, _, r = converged_small
+    g = oracle.mode_vectors(T, r.xs)
+    for n in range(T.ndim):
+        assert np.linalg.norm(g[n] - r.sigma * r.xs[n]) < 1e-10 * r.sigma
+
+
+def test_equal_block_norms_and_eigenvalue(converged_small):
+    """Theorem 1 (P2): an NEPv solution with lambda != 0 has equal block
+    norms; sigma is an eigenvalue of J(x*) with eigenvector x~."""
+    T, _, r = converged_small
+    J = oracle.j_matrix(oracle.blocks(T, r.xs), T.shape)
+    w, V = np.linalg.eigh(J)
+    i = int(np.argmin(np.abs(w - r.sigma)))
+    assert abs(w[i] - r.sigma) < 1e-10 * r.sigma
+    y = V[:, i]
+    norms = [np.linalg.norm(b) for b in oracle.split(y, T.shape)]
+    np.testing.assert_allclose(norms, 1 / math.sqrt(3), rtol=1e-8)
+
+
+def test_sigma_bounds(converged_small):
+    """sigma <= ||T||_F (rank-one approximation error >= 0) and, planted,
+    sigma >= T(a, b, c) (the planted factors are feasible)."""
+    T, fac, r = converged_small
+    assert r.sigma <= np.linalg.norm(T) * (1 + 1e-14)
+    assert r.sigma >= oracle.objective(T, fac) - 1e-12
+    resid = T - r.sigma * oracle.outer(r.xs)
+    # P6: ||T - sigma u o v o w||^2 = ||T||^2 - sigma^2 at a KKT point
+    assert np.sum(resid ** 2) == pytest.approx(np.sum(T ** 2) - r.sigma ** 2, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P7 brute force over the spheres on tiny tensors, P5 largest magnitude
+# ---------------------------------------------------------------------------
+
+def _sphere_grid(dim, k):
+    if dim == 1:
+        return np.ones((1, 1))
+    if dim == 2:
+        th = np.linspace(0, np.pi, k, endpoint=False)
+        return np.stack([np.cos(th), np.sin(th)], 1)
+    if dim == 3:
+        th = np.linspace(0, np.pi, k)
+        ph = np.linspace(0, 2 * np.pi, 2 * k, endpoint=False)
+        TH, PH = np.meshgrid(th, ph)
+        return np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], -1).reshape(-1, 3)
+    raise ValueError
+
+
+def brute_force_max(T, k):
+    """Global max of T(u) over unit u: grid over u_2..u_N, closed-form best
+    u_1 = normalise(T x_{k>1} u_k), then HOPM polish of the best grid points."""
+    dims = T.shape
+    N = len(dims)
+    grids = [_sphere_grid(d, k) for d in dims[1:]]
+    vals = []
+    combos = list(itertools.product(*[range(len(g)) for g in grids]))
+    X = np.asarray(T, dtype=np.float64)
+    # value = || T x_2 u_2 ... x_N u_N ||
+    cur = X
+    # vectorised: contract modes from last to second with all grid points
+    out = np.tensordot(cur, grids[-1], axes=([N - 1], [1]))  # (I1..I_{N-1}, G_N)
+    for m in range(N - 2, 0, -1):
+        # contract mode m with grid m, keeping grid axes
+        out = np.moveaxis(np.tensordot(out, grids[m - 1], axes=([m], [1])), -1, m)
+    # out shape (I1, G_2, ..., G_N)
+    vals = np.sqrt(np.sum(out ** 2, axis=0))
+    flat = np.argsort(vals.ravel())[::-1][:30]
+    best = 0.0
+    for f in flat:
+        gi = np.unravel_index(f, vals.shape)
+        x0 = [np.ones(dims[0])] + [grids[m][gi[m]] for m in range(N - 1)]
+        r = oracle.hopm(T, oracle.stack(x0), tol=1e-15, max_iter=5000)
+        best = max(best, r.sigma)
+    return max(best, float(vals.max()))
+
+
+@pytest.mark.parametrize("dims,k", [((2, 2, 2), 720), ((3, 3, 3), 48), ((2, 2, 2, 2), 160)])
+def test_bruteforce_global_max(dims, k):
+    """P7: best-of-many-starts HOSCF reaches the global maximum found by
+    brute force, every start is below it, and at the best start sigma is the
+    largest-magnitude eigenvalue of J(x*) (Theorem 3)."""
+    T = rand_tensor(dims, 101 + len(dims))
+    gmax = brute_force_max(T, k)
+    best = None
+    for s in range(20):
+        r = oracle.hoscf(T, synth.init_factors(dims, 500 + s), tol=1e-13, max_iter=3000)
+        assert r.sigma <= gmax * (1 + 1e-9)
+        if best is None or r.sigma > best.sigma:
+            best = r
+    assert best.sigma == pytest.approx(gmax, rel=1e-8)
+    J = oracle.j_matrix(oracle.blocks(T, best.xs), dims)
+    w = np.linalg.eigvalsh(J)
+    assert np.max(np.abs(w)) == pytest.approx(best.sigma, rel=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# P8 printed values (Example 2), P9 loose statistics (Example 1)
+# ---------------------------------------------------------------------------
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def test_example2_exp_rho():
+    """Table 2 / Table 3: EXP 30^3, rho = |lambda| / ||A||_F = 0.82."""
+    gold = _golden("example2_rho.json")["EXP"]
+    T = synth.exp_tensor(gold["n"], gold["order"])
+    nrm = np.linalg.norm(T)
+    rhos = []
+    for s in range(5):
+        x0 = synth.init_factors(T.shape, 700 + s, uniform=True)
+        r = oracle.hoscf(T, x0, tol=1e-4, max_iter=500)
+        rhos.append(r.sigma / nrm)
+    assert np.round(np.mean(rhos), 2) == gold["rho"]
+
+
+def test_example2_arcsin_rho():
+    """Table 2 / Table 3: ARCSIN 20^4, best rho = 0.66 (entry formula read
+    as arcsin((-1)^(i_j) j / i_j))."""
+    gold = _golden("example2_rho.json")["ARCSIN"]
+    T = synth.arcsin_tensor(gold["n"], gold["order"])
+    nrm = np.linalg.norm(T)
+    best = 0.0
+    for s in range(6):
+        x0 = synth.init_factors(T.shape, 800 + s, uniform=True)
+        r = oracle.hoscf(T, x0, algo="ihoscf", tol=1e-4, max_iter=500)
+        best = max(best, r.sigma / nrm)
+    assert abs(best - gold["rho"]) <= gold["printed_pm"]
+
+
+def test_example1_lambda_loose():
+    """Table 1, d = 3: the mean of lambda over starts and tensors lies in a
+    loose window around the printed 8.12 +- 0.52 (seed unknown)."""
+    gold = _golden("table1_lambda.json")["HOSCF"]["3"]
+    lams = []
+    for t in range(6):
+        T = rand_tensor((10, 10, 10), 900 + t)
+        for s in range(3):
+            r = oracle.hoscf(T, synth.init_factors(T.shape, 950 + 3 * t + s, uniform=True), tol=1e-4)
+            lams.append(r.sigma)
+    assert abs(np.mean(lams) - gold[0]) < 3 * gold[1]
+
+
+# ---------------------------------------------------------------------------
+# Signs, iHOSCF, RQI, HOPM
+# ---------------------------------------------------------------------------
+
+def test_canonical_sign_invariance():
+    """Flipping the signs of initial blocks gives the identical output
+    (sign equivariance of J, Theorem 1 P1, plus the fixed representative)."""
+    T, _ = synth.planted_rank_one((7, 6, 5, 4), 9.0, 55, dtype=np.float64)
+    x0 = synth.init_factors(T.shape, 56)
+    ref = oracle.hoscf(T, x0, tol=1e-12, max_iter=1000)
+    for flips in [(1, -1, 1, 1), (-1, -1, -1, 1), (1, 1, 1, -1)]:
+        xs = [f * v for f, v in zip(flips, oracle.split(x0, T.shape))]
+        r = oracle.hoscf(T, oracle.stack(xs), tol=1e-12, max_iter=1000)
+        assert r.sigma == pytest.approx(ref.sigma, rel=1e-13)
+        for a, b in zip(r.xs, ref.xs):
+            np.testing.assert_allclose(a, b, atol=1e-9)
+    # the representative: largest-|entry| of u_2..u_N positive, sigma >= 0
+    assert ref.sigma > 0
+    for v in ref.xs[1:]:
+        assert v[np.argmax(np.abs(v))] > 0
+
+
+def test_canonical_signs_rule():
+    xs = [np.array([1.0, 2.0]), np.array([0.5, -3.0, 3.0]), np.array([-2.0, 1.0])]
+    out = oracle.canonical_signs(xs)
+    # u_2: |-3| ties |3|, lowest index wins -> entry -3 made positive (flip);
+    # u_3: -2 made positive (flip); u_1 flipped twice
+    np.testing.assert_array_equal(out[1], [-0.5, 3.0, -3.0])
+    np.testing.assert_array_equal(out[2], [2.0, -1.0])
+    np.testing.assert_array_equal(out[0], [1.0, 2.0])
+
+
+def test_rqi_step_spectral_form():
+    """Section 4.4: z = (J - rho I)^{-1} x equals sum_i (y_i'x)/(mu_i - rho) y_i
+    (spectral form) up to normalisation."""
+    rng = np.random.default_rng(61)
+    B = rng.standard_normal((9, 9))
+    J = B + B.T
+    x = rng.standard_normal(9)
+    x /= np.linalg.norm(x)
+    w, V = np.linalg.eigh(J)
+    rho = float(x @ J @ x)
+    spec = V @ ((V.T @ x) / (w - rho))
+    spec /= np.linalg.norm(spec)
+    z = oracle.rqi_step(J, x)
+    if abs(float(spec @ J @ spec)) > abs(rho):
+        assert z is not None
+        assert oracle.angle(z, spec) < 1e-10
+    else:
+        assert z is None
+
+
+def test_rqi_reject_when_singular():
+    J = np.diag([2.0, 1.0, 0.0])
+    x = np.array([0.0, 0.0, 1.0])  # rho = 0 exactly: J - rho I singular
+    assert oracle.rqi_step(J, x) is None
+
+
+def test_ihoscf_same_point_fewer_iterations():
+    """Section 4.4: iHOSCF reaches the same point with fewer iterations."""
+    its_h, its_i = [], []
+    for s in range(4):
+        T, _ = synth.planted_rank_one((10, 9, 8), 8.0, 70 + s, dtype=np.float64)
+        x0 = synth.init_factors(T.shape, 80 + s)
+        a = oracle.hoscf(T, x0, tol=1e-11, max_iter=3000)
+        b = oracle.hoscf(T, x0, algo="ihoscf", tol=1e-11, max_iter=3000)
+        assert a.status == b.status == oracle.OK
+        assert b.sigma == pytest.approx(a.sigma, rel=1e-10)
+        its_h.append(a.iters)
+        its_i.append(b.iters)
+    assert sum(its_i) < sum(its_h)
+
+
+def test_hopm_agrees_on_planted():
+    """P13: HOPM (Section 1) and HOSCF find the same sigma on a strongly
+    planted tensor from the same start."""
+    T, _ = synth.planted_rank_one((12, 11, 10), 40.0, 90, dtype=np.float64)
+    x0 = synth.init_factors(T.shape, 91)
+    a = oracle.hoscf(T, x0, tol=1e-13, max_iter=500)
+    b = oracle.hopm(T, x0, tol=1e-15, max_iter=500)
+    assert a.sigma == pytest.approx(b.sigma, rel=1e-12)
+    for u, v in zip(a.xs, b.xs):
+        assert oracle.angle(u, v) < 1e-6
+
+
+def test_zero_block_is_degenerate():
+    with pytest.raises(oracle.Degenerate):
+        oracle.normalize_blocks(np.array([1.0, 0.0, 0.0, 0.0, 2.0]), (2, 2, 1))
+
+
+# ---------------------------------------------------------------------------
+# Greedy deflation (Section 1, Example 3)
+# ---------------------------------------------------------------------------
+
+def test_deflation_odeco_exact():
+    """For an orthogonally decomposable tensor sum_r lam_r a_r o b_r o c_r
+    (orthonormal factor sets), the greedy rank-one update recovers the terms
+    in decreasing order, and res_r follows ||A^(r+1)||^2 = ||A^(r)||^2 - lam_r^2."""
+    rng = np.random.default_rng(123)
+    dims = (6, 5, 7)
+    R = 3
+    Q = [np.linalg.qr(rng.standard_normal((d, d)))[0][:, :R] for d in dims]
+    lams = np.array([9.0, 5.0, 2.0])
+    T = sum(lams[r] * oracle.outer([Q[n][:, r] for n in range(3)]) for r in range(R))
+    x0s = [synth.init_factors(dims, 130 + r) for r in range(R)]
+    results, res = oracle.greedy_deflation(T, x0s, R, tol=1e-13, max_iter=2000)
+    sig = [r.sigma for r in results]
+    # local maxima of odeco tensors are exactly the components; the greedy
+    # order from these starts must give the components, largest first
+    np.testing.assert_allclose(sorted(sig, reverse=True), lams, rtol=1e-10)
+    tot = np.sum(lams ** 2)
+    remaining = tot
+    for r in range(R):
+        remaining -= sig[r] ** 2
+        assert res[r] == pytest.approx(math.sqrt(max(remaining, 0) / tot), abs=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# Derivatives: finite differences in FP64
+# ---------------------------------------------------------------------------
+
+def _solve_fn(x_start, gs, gx, dims):
+    def loss(Tp):
+        r = oracle.hoscf(Tp, x_start, tol=1e-15, max_iter=400)
+        val = gs * r.sigma
+        for n in range(len(dims)):
+            val += float(gx[n] @ r.xs[n])
+        return val
+    return loss
+
+
+@pytest.mark.parametrize("dims", [(5, 4, 3), (4, 3, 3, 2)])
+def test_grad_solve_finite_differences(dims):
+    """P10: dsigma/dT = u_1 o ... o u_N, and the full gradient of
+    g_s * sigma + sum_n w_n'u_n matches central differences (h = 1e-6)."""
+    T, _ = synth.planted_rank_one(dims, 6.0, 150, dtype=np.float64)
+    r = oracle.hoscf(T, synth.init_factors(dims, 151), tol=1e-15, max_iter=2000)
+    assert r.status == oracle.OK
+    rng = np.random.default_rng(152)
+    gx = [rng.standard_normal(d) for d in dims]
+    dT_sigma, _ = oracle.grad_solve(T, r.xs, r.sigma, 1.0, None)
+    np.testing.assert_allclose(dT_sigma, oracle.outer(r.xs), atol=1e-14)
+    dT, mu = oracle.grad_solve(T, r.xs, r.sigma, 1.0, gx)
+    for n in range(len(dims)):
+        assert abs(float(mu[n] @ r.xs[n])) < 1e-10  # tangent (X' mu = 0)
+    loss = _solve_fn(r.x, 1.0, gx, dims)
+    for t in range(3):
+        E = rng.standard_normal(dims)
+        fd = oracle.fd_directional(loss, T, E, h=1e-6)
+        an = float(np.sum(dT * E))
+        assert fd == pytest.approx(an, rel=2e-6, abs=2e-7)
+
+
+def test_grad_ttvc_finite_differences():
+    """Adjoint of the sweep outputs (g_n, sigma) w.r.t. T and the factors."""
+    dims = (4, 5, 3)
+    rng = np.random.default_rng(160)
+    T = rng.standard_normal(dims)
+    xs = rand_unit(dims, 161)
+    gbar = [rng.standard_normal(d) for d in dims]
+    sbar = 0.7
+
+    def f(Tp, xp):
+        g = oracle.mode_vectors(Tp, xp)
+        return sum(float(gbar[n] @ g[n]) for n in range(3)) + sbar * oracle.objective(Tp, xp)
+
+    dT, dx = oracle.grad_ttvc(T, xs, gbar, sbar)
+    E = rng.standard_normal(dims)
+    fd = (f(T + 1e-6 * E, xs) - f(T - 1e-6 * E, xs)) / 2e-6
+    assert fd == pytest.approx(float(np.sum(dT * E)), rel=1e-7)
+    for m in range(3):
+        e = rng.standard_normal(dims[m])
+        xp = [v.copy() for v in xs]
+        xm = [v.copy() for v in xs]
+        xp[m] = xp[m] + 1e-6 * e
+        xm[m] = xm[m] - 1e-6 * e
+        fdx = (f(T, xp) - f(T, xm)) / 2e-6
+        assert fdx == pytest.approx(float(dx[m] @ e), rel=1e-7)
