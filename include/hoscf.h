@@ -1,0 +1,234 @@
+/*
+ * hoscf.h -- C ABI of libhoscf, the MI355X (gfx950) HOSCF / iHOSCF library.
+ *
+ * Problem (Section 2, eq. rank-one approx-2): for a dense order-N tensor T,
+ * maximise sigma = T x_1 u_1 x_2 u_2 ... x_N u_N over unit vectors u_n.  The
+ * solver is the higher-order self-consistent field iteration (Section 4,
+ * Algorithm 1) on the eigenvector-dependent eigenproblem J(x)x = lambda x of
+ * Section 3 (eq. map, eq. submatrix, eq. nepv-1), optionally with the
+ * Rayleigh-quotient step of iHOSCF (Section 4.4).
+ *
+ * Conventions shared by every call:
+ *   - All tensor and vector arguments are DEVICE pointers (hipMalloc'd or
+ *     torch CUDA memory) unless the name ends in _host.  The caller owns every
+ *     buffer; the library never frees caller memory.
+ *   - Tensors are dense, C-order contiguous (last mode fastest), 16-byte
+ *     aligned.  Factor vectors are stacked: x = [x_1; x_2; ...; x_N], FP64,
+ *     length D = I_1 + ... + I_N (the blocks index_n of eq. factor).
+ *   - J blocks are stored packed, raw (WITHOUT the 1/(N-1) factor of eq. map):
+ *     A_{1,2}, A_{1,3}, ..., A_{1,N}, A_{2,3}, ..., A_{N-1,N}; block (m,n) is
+ *     I_m x I_n row-major, A_{m,n}[i,j] = (T x_{k not in {m,n}} u_k)[i,j]
+ *     (eq. submatrix).  Element type: double for FP64 tensors, float
+ *     otherwise.  Blocks of FP8 tensors include the dequantisation scale.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call is stream-ordered; only hoscf_solve synchronises.
+ *   - `ws` is a caller-provided device workspace of at least the size that
+ *     hoscf_workspace_size returns for the same arguments; no call except
+ *     hoscf_batch_plan_create allocates device memory.
+ *   - Calls are reentrant; the library holds no global mutable state apart
+ *     from a read-only tile table.  Two calls that share a workspace must not
+ *     overlap in time.
+ *   - Return value: an hoscf_status (0 = OK).  On INVALID_ARG or
+ *     WORKSPACE_TOO_SMALL nothing is launched.
+ */
+#ifndef HOSCF_H
+#define HOSCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOSCF_MAX_ORDER 8
+
+typedef enum {
+    HOSCF_OK = 0,
+    HOSCF_NOT_CONVERGED = 1,       /* max_iter or stagnation; outputs = last iterate, valid */
+    HOSCF_INVALID_ARG = -1,        /* order not in [2,8], dim <= 0, NULL pointer, bad dtype */
+    HOSCF_HIP_ERROR = -2,          /* a HIP runtime call failed (or a device wait timed out) */
+    HOSCF_NONFINITE = -3,          /* NaN/Inf met in blocks or iterates */
+    HOSCF_DEGENERATE = -4,         /* a factor block of the eigenvector is 0 (eq. factor) or T = 0 */
+    HOSCF_WORKSPACE_TOO_SMALL = -5
+} hoscf_status;
+
+typedef enum {
+    HOSCF_F64 = 0,
+    HOSCF_F32 = 1,
+    HOSCF_BF16 = 2,      /* bfloat16 storage, FP32 accumulation */
+    HOSCF_FP8E4M3 = 3    /* OCP E4M3 storage (max 448) with a per-tensor scale, FP32 accumulation */
+} hoscf_dtype;
+
+typedef enum {
+    HOSCF_OP_TTVC = 0,
+    HOSCF_OP_SOLVE = 1,
+    HOSCF_OP_BACKWARD = 2,
+    HOSCF_OP_TTVC_BACKWARD = 3,
+    HOSCF_OP_QUANTIZE = 4
+} hoscf_op;
+
+/* A dense tensor on the device. */
+typedef struct {
+    int32_t order;                    /* N, 2..8 */
+    int64_t dims[HOSCF_MAX_ORDER];    /* I_1..I_N, each >= 1 */
+    int32_t dtype;                    /* hoscf_dtype of `data` */
+    const void* data;                 /* device, C-order */
+    float scale;                      /* FP8: value = code * scale; ignored otherwise (use 1) */
+    const void* data_f32;             /* optional FP32 copy of the same tensor (precision form:
+                                         refinement sweeps read it); NULL if none */
+} hoscf_tensor;
+
+/* Solver options (Algorithm 1 and Section 4.3/4.4). */
+typedef struct {
+    int32_t algo;            /* 0 = HOSCF, 1 = iHOSCF */
+    double tol;              /* stop when the residual of eq. stop-3 (read as the NEPv residual at
+                                the iterate, see DESIGN) is <= tol */
+    int32_t max_iter;        /* maximum number of eigen-steps */
+    double tol_lp;           /* precision form: low-precision sweeps until residual <= tol_lp */
+    int32_t max_refine;      /* precision form: max FP32 refinement iterations (0 = max_iter) */
+    int32_t canonical_sign;  /* 1 (default): fix the sign representative every iteration */
+    int32_t stall_iters;     /* >0: stop NOT_CONVERGED after this many iterations without a new
+                                lowest residual; 0 = off */
+} hoscf_options;
+
+/* Per-solve report. */
+typedef struct {
+    int32_t iters;           /* eigen-steps taken */
+    int32_t sweeps;          /* TTVc sweeps over the tensor (all precisions) */
+    int32_t rqi_accepted;    /* iHOSCF Rayleigh steps accepted */
+    int32_t status;          /* hoscf_status of the solve */
+    int32_t lp_sweeps;       /* sweeps over the low-precision copy (precision form) */
+    int32_t lanczos_steps;   /* total Lanczos steps in all eigen-steps */
+    double residual;         /* residual at the returned iterate */
+    double lambda;           /* sigma at the returned iterate (>= 0) */
+} hoscf_info;
+
+/* Device bytes of workspace that `op` needs for tensor T (opts may be NULL). */
+size_t hoscf_workspace_size(int op, const hoscf_tensor* T, const hoscf_options* opts);
+
+/* Human-readable name of a status code. */
+const char* hoscf_status_string(int status);
+
+/*
+ * hoscf_ttvc -- one TTVc sweep (eq. submatrix, eq. map; Section 4.2: the
+ * J-build, the cost bottleneck) at the factors x.
+ *   x       [D] FP64 device: the factors; each block is normalised on the fly
+ *           (eq. factor), so x need not be unit.
+ *   blocks  packed raw J blocks (layout above).
+ *   g       [D] FP64 device: mode vectors g_n = T x_{k != n} u_k (eq. kkt LHS),
+ *           formed as the mean over m != n of A_{n,m} u_m.
+ *   scalars [4] FP64 device: sigma = u_1' g_1 (= T(u)), the residual
+ *           sqrt(sum_n ||g_n - sigma u_n||^2 / N) / (||J||_F + |sigma|),
+ *           ||J||_F = sqrt(2 sum ||A_{m,n}||_F^2)/(N-1), and a non-finite flag.
+ * Reads T once from HBM; all blocks come from that one pass.
+ */
+int hoscf_ttvc(const hoscf_tensor* T, const double* x, void* blocks, double* g,
+               double* scalars, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * hoscf_solve -- HOSCF (Algorithm 1) or iHOSCF (Section 4.4) from x0.
+ *   x0      [D] FP64 device initial factors (blocks normalised on entry).
+ *   x_out   [D] FP64 device: unit factors of the returned iterate, signs
+ *           canonical (largest-|entry| of u_2..u_N positive) and sigma >= 0
+ *           (Algorithm 1, final sign fix).  May alias x0.
+ *   sigma_host, info_host: host pointers, filled before return (either may be NULL).
+ * Precision form: if T->dtype is BF16/FP8 and T->data_f32 is set, sweeps run
+ * on the low-precision copy until the residual reaches opts->tol_lp (or
+ * stalls), then FP32 refinement sweeps on data_f32 run to opts->tol; the
+ * eigen-step, the Rayleigh step and sigma stay FP64.
+ * Returns OK, NOT_CONVERGED (outputs valid), or an error.  Synchronises `stream`.
+ */
+int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* opts,
+                double* x_out, double* sigma_host, hoscf_info* info_host,
+                void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * hoscf_quantize -- FP32 -> BF16 (round to nearest even) or FP8 E4M3 (OCP;
+ * scale = amax/448 in binary32, codes = RNE(x / scale), saturating at 448).
+ *   src [n] float device; dst [n] uint16 (BF16) or uint8 (FP8) device;
+ *   scale_dev [1] float device: the scale (1 for BF16).
+ */
+int hoscf_quantize(const float* src, int64_t n, int dtype, void* dst, float* scale_dev,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * hoscf_backward -- gradient of a loss L(sigma, u) through hoscf_solve
+ * (project addition; derived from eq. kkt by implicit differentiation).
+ *   x, sigma  a converged solve's factors and sigma.
+ *   g_sigma   dL/dsigma;  g_x [D] FP64 device dL/du (NULL = 0).
+ *   grad_T    same shape as T; float (grad_dtype = HOSCF_F32) or double (HOSCF_F64):
+ *             dL/dT = g_sigma u_1 o ... o u_N - sum_n u_1 o .. o mu_n o .. o u_N,
+ *             with mu tangent (u_n' mu_n = 0) solving P(M - sigma I)P mu = P g_x,
+ *             M = (N-1) J(x), P the blockwise projector onto the tangent space.
+ *   mu_out    [D] FP64 device, optional (NULL).
+ *   info      [2] FP64 device, optional: CG iterations and final relative residual.
+ * T is read once (one sweep for the blocks); grad_T is written once.
+ */
+int hoscf_backward(const hoscf_tensor* T, const double* x, double sigma, double g_sigma,
+                   const double* g_x, void* grad_T, int grad_dtype, double* mu_out,
+                   double* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * hoscf_ttvc_backward -- adjoint of hoscf_ttvc's differentiable outputs
+ * (g, sigma) for cotangents gbar [D] (NULL = 0) and sigma_bar:
+ *   grad_T = sum_n u_1 o .. o gbar_n o .. o u_N + sigma_bar u_1 o ... o u_N
+ *   grad_x = the gradient w.r.t. the unit factors u:
+ *            grad_x_m = sum_{n != m} A_{m,n} gbar_n + sigma_bar g_m
+ * `blocks` and `g` are the forward's outputs at the same x (x unit).
+ * grad_T may be NULL (factor adjoint only); grad_x may be NULL.
+ */
+int hoscf_ttvc_backward(const hoscf_tensor* T, const double* x, const void* blocks,
+                        const double* g, const double* gbar, double sigma_bar,
+                        void* grad_T, int grad_dtype, double* grad_x,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * hoscf_profile_sweep -- measurement helper (not part of the method): runs
+ * `reps` sweeps exactly as hoscf_ttvc does (same plan, same workspace size)
+ * and times them with HIP events on `stream`.
+ *   out_ms [3] host: mean milliseconds per sweep of (0) the whole sweep,
+ *          (1) the three-output TTVc kernel launches only (all recursion
+ *          levels), (2) the level-1 TTVc kernel launch alone (the pass that
+ *          streams T from HBM).
+ *   out_bytes [1] host (optional): algorithmic bytes of T per sweep.
+ * Synchronises `stream`.
+ */
+int hoscf_profile_sweep(const hoscf_tensor* T, const double* x, void* blocks, double* g, int reps,
+                        double* out_ms, int64_t* out_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- batched form: many small order-3 tensors, greedy rank-R deflation ---- */
+
+typedef struct hoscf_plan hoscf_plan;
+
+/*
+ * hoscf_batch_plan_create -- plan for B tensors (host descriptors; each
+ * order 3, FP32, every dim in [1, 96]) solved with greedy rank-one
+ * deflation (Section 1; Example 3): for r = 1..R, HOSCF on
+ * T_b - sum_{s<r} sigma_s u_s1 o u_s2 o u_s3.  Uploads descriptors, orders
+ * work largest first and reads the tile table.  The ONLY allocating call.
+ */
+int hoscf_batch_plan_create(int B, const hoscf_tensor* host_descs, int R,
+                            const hoscf_options* opts, hoscf_plan** out);
+void hoscf_plan_destroy(hoscf_plan* plan);
+size_t hoscf_batch_workspace_size(const hoscf_plan* plan);
+
+/*
+ * hoscf_solve_batched -- run the plan in ONE persistent launch (capture-safe:
+ * no allocation, no synchronisation, no host reads).
+ *   x0        FP64 device, packed [b][r][D_b] (b-major, then r, then the
+ *             stacked factors of tensor b).
+ *   x_out     same layout: unit factors per rank-one term.
+ *   sigma_out [B*R] FP64 device.
+ *   status_out[B*R] int32 device (hoscf_status per term).
+ *   iters_out [B*R] int32 device, optional (NULL).
+ */
+int hoscf_solve_batched(const hoscf_plan* plan, const double* x0, double* x_out,
+                        double* sigma_out, int32_t* status_out, int32_t* iters_out,
+                        void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOSCF_H */

@@ -1,0 +1,320 @@
+// C ABI of libhoscf: argument checks, workspace layout and the host loop of
+// HOSCF (Algorithm 1) and iHOSCF (Section 4.4).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "post.h"
+#include "quant.h"
+#include "ttvc.h"
+#include "tuning.h"
+
+using namespace hoscf;
+
+namespace {
+
+__global__ void init_state_kernel(SolveState* st) {
+    if (threadIdx.x == 0) {
+        SolveState z{};
+        *st = z;
+    }
+}
+
+// x_out = x with block 1 negated when sigma < 0 (Algorithm 1, final sign fix).
+__global__ __launch_bounds__(256) void finalize_kernel(const double* x, int64_t D, int64_t I1,
+                                                       const SolveState* st, double* x_out) {
+    const bool flip = st->sigma < 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < D; r += (int64_t)gridDim.x * 256)
+        x_out[r] = (flip && r < I1) ? -x[r] : x[r];
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const double* src, int64_t n, double* dst) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) dst[r] = src[r];
+}
+
+bool valid_tensor(const hoscf_tensor* T) {
+    if (!T || !T->data) return false;
+    if (T->order < 2 || T->order > HOSCF_MAX_ORDER) return false;
+    if (T->dtype < HOSCF_F64 || T->dtype > HOSCF_FP8E4M3) return false;
+    double total = 1.0;
+    for (int i = 0; i < T->order; ++i) {
+        if (T->dims[i] < 1) return false;
+        total *= (double)T->dims[i];
+    }
+    if (total > 9.0e18) return false;
+    if (T->dtype == HOSCF_FP8E4M3 && !(T->scale > 0.f && std::isfinite(T->scale))) return false;
+    return true;
+}
+
+int acc_fmt(int dtype) { return dtype == HOSCF_F64 ? HOSCF_F64 : HOSCF_F32; }
+
+hoscf_options default_options() {
+    hoscf_options o{};
+    o.algo = 0;
+    o.tol = 1e-10;
+    o.max_iter = 500;
+    o.tol_lp = 1e-3;
+    o.max_refine = 0;
+    o.canonical_sign = 1;
+    o.stall_iters = 0;
+    return o;
+}
+
+constexpr int kDefaultKmax = 255;
+
+// Everything hoscf_solve / hoscf_ttvc place in the workspace.
+struct SolveLayout {
+    SweepPlan sweep;      // sweeps over T->data (storage dtype)
+    SweepPlan sweep32;    // refinement sweeps over T->data_f32 (precision form only)
+    bool two_phase = false;
+    PostPlan post;
+    PostPlan post32;
+    SolveState* st = nullptr;
+    double* g = nullptr;
+    double* x = nullptr;   // FP64 iterate (solve) when not aliased to a sweep's unit buffer
+    size_t used = 0;
+    bool ok = false;
+
+    bool build(const hoscf_tensor& T, void* blocks_out, bool solve, int kmax, void* ws, size_t ws_bytes) {
+        Arena ar(ws, ws_bytes);
+        const SweepTuning tune = lookup_tuning(T);
+        st = ar.take<SolveState>(1);
+        two_phase = solve && (T.dtype == HOSCF_BF16 || T.dtype == HOSCF_FP8E4M3) && T.data_f32 != nullptr;
+        sweep.build(T, T.dtype, T.data, T.dtype == HOSCF_FP8E4M3 ? T.scale : 1.f, blocks_out, ar, tune);
+        const int maxwg = post_max_workgroups(sweep.f64);
+        post.build(sweep.map, sweep.f64, solve ? kmax : 1, maxwg, ar);
+        if (two_phase) {
+            hoscf_tensor T32 = T;
+            T32.dtype = HOSCF_F32;
+            T32.data = T.data_f32;
+            sweep32.build(T32, HOSCF_F32, T.data_f32, 1.f, nullptr, ar, lookup_tuning(T32));
+            post32 = post;  // same block geometry and precision (FP32 blocks)
+        }
+        g = ar.take<double>(sweep.map.D);
+        x = ar.take<double>(sweep.map.D);
+        used = ar.used;
+        ok = ar.ok;
+        return ok;
+    }
+};
+
+int hip_status(hipError_t e) { return e == hipSuccess ? HOSCF_OK : HOSCF_HIP_ERROR; }
+
+}  // namespace
+
+extern "C" {
+
+const char* hoscf_status_string(int status) {
+    switch (status) {
+        case HOSCF_OK: return "OK";
+        case HOSCF_NOT_CONVERGED: return "NOT_CONVERGED";
+        case HOSCF_INVALID_ARG: return "INVALID_ARG";
+        case HOSCF_HIP_ERROR: return "HIP_ERROR";
+        case HOSCF_NONFINITE: return "NONFINITE";
+        case HOSCF_DEGENERATE: return "DEGENERATE";
+        case HOSCF_WORKSPACE_TOO_SMALL: return "WORKSPACE_TOO_SMALL";
+    }
+    return "UNKNOWN";
+}
+
+size_t hoscf_workspace_size(int op, const hoscf_tensor* T, const hoscf_options* opts) {
+    (void)opts;
+    if (op == HOSCF_OP_QUANTIZE) return 256;
+    if (!valid_tensor(T)) return 0;
+    SolveLayout lay;
+    switch (op) {
+        case HOSCF_OP_TTVC:
+            lay.build(*T, reinterpret_cast<void*>(0x1000), false, 1, nullptr, 0);
+            return lay.used;
+        case HOSCF_OP_SOLVE:
+            lay.build(*T, nullptr, true, kDefaultKmax, nullptr, 0);
+            return lay.used;
+        default: break;
+    }
+    return hoscf_extra_workspace_size(op, T);
+}
+
+int hoscf_ttvc(const hoscf_tensor* T, const double* x, void* blocks, double* g, double* scalars, void* ws,
+               size_t ws_bytes, void* stream) {
+    if (!valid_tensor(T) || !x || !blocks || !g) return HOSCF_INVALID_ARG;
+    SolveLayout lay;
+    if (!ws || !lay.build(*T, blocks, false, 1, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
+    HOSCF_TRY(hipGetLastError());
+    HOSCF_TRY(lay.sweep.run(x, lay.st, s));
+    HOSCF_TRY(lay.post.run(kPostEpilogue, lay.sweep.blocks, lay.sweep.blocksT, lay.sweep.xu, g, lay.st, scalars, 0.0, 0.0, 0.0, 1, s));
+    return HOSCF_OK;
+}
+
+int hoscf_profile_sweep(const hoscf_tensor* T, const double* x, void* blocks, double* g, int reps, double* out_ms,
+                        int64_t* out_bytes, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_tensor(T) || !x || !blocks || !g || !out_ms || reps < 1) return HOSCF_INVALID_ARG;
+    SolveLayout lay;
+    if (!ws || !lay.build(*T, blocks, false, 1, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nn = std::max(1, lay.sweep.num_nodes());
+    std::vector<hipEvent_t> ev(2 * nn + 2);
+    for (auto& e : ev) HOSCF_TRY(hipEventCreate(&e));
+    double tot = 0.0, k1 = 0.0, k1root = 0.0;
+    int rc = HOSCF_OK;
+    for (int r = 0; r < reps && rc == HOSCF_OK; ++r) {
+        hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
+        if (hipEventRecord(ev[2 * nn], s) != hipSuccess) rc = HOSCF_HIP_ERROR;
+        if (rc == HOSCF_OK && lay.sweep.run(x, lay.st, s, lay.sweep.num_nodes() ? ev.data() : nullptr) != hipSuccess)
+            rc = HOSCF_HIP_ERROR;
+        if (rc == HOSCF_OK && lay.post.run(kPostEpilogue, lay.sweep.blocks, lay.sweep.blocksT, lay.sweep.xu, g, lay.st, nullptr, 0.0, 0.0,
+                                           0.0, 1, s) != hipSuccess)
+            rc = HOSCF_HIP_ERROR;
+        if (rc == HOSCF_OK && hipEventRecord(ev[2 * nn + 1], s) != hipSuccess) rc = HOSCF_HIP_ERROR;
+        if (rc == HOSCF_OK && hipEventSynchronize(ev[2 * nn + 1]) != hipSuccess) rc = HOSCF_HIP_ERROR;
+        if (rc != HOSCF_OK) break;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ev[2 * nn], ev[2 * nn + 1]);
+        tot += ms;
+        for (int i = 0; i < lay.sweep.num_nodes(); ++i) {
+            hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+            k1 += ms;
+            if (i == 0) k1root += ms;
+        }
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    if (rc != HOSCF_OK) return rc;
+    out_ms[0] = tot / reps;
+    out_ms[1] = k1 / reps;
+    out_ms[2] = k1root / reps;
+    if (out_bytes) *out_bytes = lay.sweep.bytes_read;
+    return HOSCF_OK;
+}
+
+int hoscf_quantize(const float* src, int64_t n, int dtype, void* dst, float* scale_dev, void* ws, size_t ws_bytes,
+                   void* stream) {
+    if (!src || !dst || !scale_dev || n < 0) return HOSCF_INVALID_ARG;
+    if (dtype != HOSCF_BF16 && dtype != HOSCF_FP8E4M3) return HOSCF_INVALID_ARG;
+    if (n == 0) return HOSCF_OK;
+    return quantize(src, n, dtype, dst, scale_dev, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* opts_in, double* x_out,
+                double* sigma_host, hoscf_info* info_host, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_tensor(T) || !x0 || !x_out) return HOSCF_INVALID_ARG;
+    const hoscf_options opts = opts_in ? *opts_in : default_options();
+    if (opts.algo != 0 && opts.algo != 1) return HOSCF_INVALID_ARG;
+    if (opts.max_iter < 0 || !(opts.tol >= 0.0)) return HOSCF_INVALID_ARG;
+    SolveLayout lay;
+    if (!ws || !lay.build(*T, nullptr, true, kDefaultKmax, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t D = lay.sweep.map.D;
+    const unsigned cgrid = (unsigned)std::min<int64_t>((D + 255) / 256, 1024);
+
+    SolveState* h = nullptr;
+    HOSCF_TRY(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(SolveState), hipHostMallocDefault));
+    hoscf_info info{};
+    int status = HOSCF_NOT_CONVERGED;
+    auto fetch = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(h, lay.st, sizeof(SolveState), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    };
+    auto body = [&]() -> int {
+        hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
+        HOSCF_TRY(hipGetLastError());
+        hipLaunchKernelGGL(copy_kernel, dim3(cgrid), dim3(256), 0, s, x0, D, lay.x);
+        HOSCF_TRY(hipGetLastError());
+        // Phase list: (sweep plan, post plan, tolerance, iteration budget)
+        struct Phase {
+            const SweepPlan* sw;
+            const PostPlan* po;
+            double tol;
+            int max_iter;
+            bool lp;
+        };
+        Phase phases[2];
+        int nph = 0;
+        if (lay.two_phase) {
+            phases[nph++] = {&lay.sweep, &lay.post, std::max(opts.tol_lp, opts.tol), opts.max_iter, true};
+            phases[nph++] = {&lay.sweep32, &lay.post32, opts.tol,
+                             opts.max_refine > 0 ? opts.max_refine : opts.max_iter, false};
+        } else {
+            phases[nph++] = {&lay.sweep, &lay.post, opts.tol, opts.max_iter, false};
+        }
+        double last_sigma = 0.0, last_res = INFINITY;
+        for (int ph = 0; ph < nph; ++ph) {
+            const Phase& P = phases[ph];
+            const bool final_phase = (ph == nph - 1);
+            // Eigen / solve tolerances track the stopping tolerance.
+            const double eig_tol = std::min(1e-8, std::max(1e-13, 1e-3 * P.tol));
+            const double solve_tol = std::min(1e-8, std::max(1e-13, 1e-2 * P.tol));
+            double* x = P.sw->xu;  // the sweep normalises lay.x into its unit buffer; iterate lives there
+            hipLaunchKernelGGL(copy_kernel, dim3(cgrid), dim3(256), 0, s, lay.x, D, x);
+            HOSCF_TRY(hipGetLastError());
+            int iters = 0, since_best = 0;
+            double best = INFINITY;
+            HOSCF_TRY(P.sw->run(x, lay.st, s));
+            info.sweeps++;
+            if (P.lp) info.lp_sweeps++;
+            int phase_status = HOSCF_NOT_CONVERGED;
+            for (;;) {
+                const bool allow = iters < P.max_iter;
+                HOSCF_TRY(P.po->run(allow ? kPostEigen : kPostEpilogue, P.sw->blocks, P.sw->blocksT, x, lay.g, lay.st, nullptr,
+                                    P.tol, eig_tol, eig_tol, opts.canonical_sign, s));
+                HOSCF_TRY(fetch());
+                info.lanczos_steps += h->lanczos;
+                last_sigma = h->sigma;
+                last_res = h->res;
+                if (h->nonfinite) return HOSCF_NONFINITE;
+                if (h->degenerate) return HOSCF_DEGENERATE;
+                if (h->res <= P.tol) {
+                    phase_status = HOSCF_OK;
+                    break;
+                }
+                if (!allow) break;
+                if (h->res < best) {
+                    best = h->res;
+                    since_best = 0;
+                } else if (++since_best >= (P.lp ? std::max(3, opts.stall_iters) : (opts.stall_iters > 0 ? opts.stall_iters : INT32_MAX))) {
+                    break;
+                }
+                ++iters;
+                info.iters++;
+                HOSCF_TRY(P.sw->run(x, lay.st, s));
+                info.sweeps++;
+                if (P.lp) info.lp_sweeps++;
+                if (opts.algo == 1) {
+                    HOSCF_TRY(P.po->run(kPostRqi, P.sw->blocks, P.sw->blocksT, x, lay.g, lay.st, nullptr, P.tol, eig_tol, solve_tol,
+                                        opts.canonical_sign, s));
+                    HOSCF_TRY(fetch());
+                    info.lanczos_steps += h->lanczos;
+                    if (h->nonfinite) return HOSCF_NONFINITE;
+                    if (h->accepted) {
+                        info.rqi_accepted++;
+                        HOSCF_TRY(P.sw->run(x, lay.st, s));
+                        info.sweeps++;
+                        if (P.lp) info.lp_sweeps++;
+                    }
+                }
+            }
+            hipLaunchKernelGGL(copy_kernel, dim3(cgrid), dim3(256), 0, s, x, D, lay.x);
+            HOSCF_TRY(hipGetLastError());
+            if (final_phase) status = phase_status;
+        }
+        // final sign fix and output
+        hipLaunchKernelGGL(finalize_kernel, dim3(cgrid), dim3(256), 0, s, lay.x, D, lay.sweep.map.dims[0], lay.st,
+                           x_out);
+        HOSCF_TRY(hipGetLastError());
+        HOSCF_TRY(hipStreamSynchronize(s));
+        info.residual = last_res;
+        info.lambda = std::fabs(last_sigma);
+        return status;
+    };
+    status = body();
+    info.status = status;
+    if (sigma_host) *sigma_host = info.lambda;
+    if (info_host) *info_host = info;
+    hipHostFree(h);
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Shared definitions of the HIP side of libhoscf (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hoscf.h"
+
+#define HOSCF_TRY(call)                                   \
+    do {                                                  \
+        hipError_t hoscf_e_ = (call);                     \
+        if (hoscf_e_ != hipSuccess) return HOSCF_HIP_ERROR; \
+    } while (0)
+
+namespace hoscf {
+
+constexpr int kWave = 64;
+constexpr int kMaxOrder = HOSCF_MAX_ORDER;
+constexpr int kMaxBlocks = kMaxOrder * (kMaxOrder - 1) / 2;
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace.  With a NULL base it only measures;
+// `ok` drops to false when the capacity is exceeded.
+struct Arena {
+    char* base;
+    size_t cap;
+    size_t used = 0;
+    bool ok = true;
+    Arena(void* b, size_t c) : base(static_cast<char*>(b)), cap(b ? c : SIZE_MAX) {}
+    template <typename T>
+    T* take(size_t count) {
+        size_t off = align_up(used);
+        used = off + align_up(count * sizeof(T) + 1);
+        if (used > cap) ok = false;
+        return (base && ok) ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
+};
+
+// Device-side solver state shared between the post-sweep kernel and the host
+// loop (one small struct, read back once per iteration).
+struct SolveState {
+    double sigma;        // u_1' g_1 at the swept iterate
+    double res;          // residual of the stopping test
+    double normJ;        // ||J||_F
+    double rho;          // Rayleigh quotient of the last Lanczos run
+    double theta;        // eigenvalue chosen by the last eigen-step
+    double ritz_res;     // final Ritz / Galerkin residual of the last Lanczos run
+    int32_t converged;   // residual <= tol at the swept iterate
+    int32_t degenerate;  // zero factor block met
+    int32_t nonfinite;   // NaN / Inf met
+    int32_t accepted;    // Rayleigh step accepted
+    int32_t lanczos;     // Lanczos steps of the last run
+    int32_t eig_unconverged;
+    int32_t barrier_timeout;
+    int32_t pad;
+    unsigned bar[2];     // grid barrier: arrival count, generation
+    // phase timestamps of the last post-sweep launch per kind (epilogue-only
+    // at [0..9], eigen / Rayleigh at [10..19]; constant 100 MHz clock):
+    // +0 start, +1 J x done, +2 sigma reduced, +3 residual reduced,
+    // +4 Lanczos step 0 done, +5 step 1 J v done, +6 step 1 done,
+    // +7 Lanczos done, +8 end; +9 Lanczos steps
+    uint64_t trace[20];
+};
+
+// Packed J-block bookkeeping for an order-N problem.
+struct BlockMap {
+    int N = 0;
+    int nblk = 0;
+    int64_t D = 0;
+    int64_t dims[kMaxOrder] = {0};
+    int64_t xoff[kMaxOrder + 1] = {0};
+    int bm[kMaxBlocks] = {0}, bn[kMaxBlocks] = {0};
+    int64_t boff[kMaxBlocks + 1] = {0};
+    int index[kMaxOrder][kMaxOrder];
+
+    void init(int order, const int64_t* d) {
+        N = order;
+        D = 0;
+        for (int n = 0; n < N; ++n) {
+            dims[n] = d[n];
+            xoff[n] = D;
+            D += d[n];
+        }
+        xoff[N] = D;
+        nblk = 0;
+        boff[0] = 0;
+        for (int m = 0; m < N; ++m)
+            for (int n = m + 1; n < N; ++n) {
+                bm[nblk] = m;
+                bn[nblk] = n;
+                index[m][n] = nblk;
+                boff[nblk + 1] = boff[nblk] + dims[m] * dims[n];
+                ++nblk;
+            }
+    }
+    int64_t total() const { return boff[nblk]; }
+};
+
+}  // namespace hoscf

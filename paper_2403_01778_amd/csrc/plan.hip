@@ -1,0 +1,175 @@
+// Sweep plan: the order-N recursion of the TTVc J-build as a list of kernel
+// launches over one workspace.
+//
+// A node is a tensor over modes (s_1, ..., s_k).  One three-output pass over
+// its view [I_{s_1}, prod middle, I_{s_k}] yields the block (s_1, s_k), the
+// contraction of the last mode (a tensor over s_1..s_{k-1}) and of the first
+// mode (over s_2..s_k).  Blocks not touching s_k are taken from the first,
+// blocks touching s_k but not s_1 from the second; a two-mode result is a
+// block and is written straight into the packed block buffer.
+#include <algorithm>
+
+#include "common.h"
+#include "ttvc.h"
+
+namespace hoscf {
+
+static inline uint32_t pair_bit(const BlockMap& bm, int a, int b) {
+    if (a > b) std::swap(a, b);
+    return 1u << bm.index[a][b];
+}
+
+void SweepPlan::add_node(int fmt, const void* in, const int* modes, int k, float scale, uint32_t need,
+                         Arena& ar, const SweepTuning& tune) {
+    const int s1 = modes[0], sk = modes[k - 1];
+    const int64_t P = map.dims[s1], Q = map.dims[sk];
+    int64_t M = 1;
+    for (int i = 1; i < k - 1; ++i) M *= map.dims[modes[i]];
+    uint32_t needL = 0, needR = 0;
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b) {
+            const uint32_t bit = pair_bit(map, modes[a], modes[b]);
+            if (!(need & bit)) continue;
+            if (b != k - 1) needL |= bit;
+            else if (a != 0) needR |= bit;
+        }
+    const bool needC = (need & pair_bit(map, s1, sk)) != 0;
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    char* blk = static_cast<char*>(blocks);
+
+    Node nd{};
+    nd.fmt = fmt;
+    nd.sh = ttvc3_shape(fmt, P, M, Q, tune.target_waves, tune.bp_min);
+    Ttvc3Args& a = nd.a;
+    a.T = in;
+    a.P = P;
+    a.M = M;
+    a.Q = Q;
+    a.xp = static_cast<char*>(xa) + map.xoff[s1] * esz;
+    a.xq = static_cast<char*>(xa) + map.xoff[sk] * esz;
+    a.scale = scale;
+    a.doL = needL != 0;
+    a.doR = needR != 0;
+    a.doC = needC;
+    a.BP = nd.sh.BP;
+    a.nq = nd.sh.nq;
+    a.QWe = nd.sh.QWe;
+    a.nmt = nd.sh.nmt;
+    if (k == 3) {
+        a.w = static_cast<char*>(xa) + map.xoff[modes[1]] * esz;
+        nd.kron = false;
+    } else {
+        nd.kron = true;
+        nd.k.nmid = k - 2;
+        nd.k.M = M;
+        for (int i = 1; i < k - 1; ++i) {
+            nd.k.off[i - 1] = map.xoff[modes[i]];
+            nd.k.dim[i - 1] = map.dims[modes[i]];
+        }
+        nd.w = ar.take<char>(M * esz);
+        a.w = nd.w;
+    }
+    // final destinations
+    void* Ldst = nullptr;
+    void* Rdst = nullptr;
+    void* Cdst = needC && blk ? blk + map.boff[map.index[s1][sk]] * esz : nullptr;
+    if (a.doL) Ldst = (k == 3) ? (blk ? blk + map.boff[map.index[s1][modes[1]]] * esz : nullptr) : ar.take<char>(P * M * esz);
+    if (a.doR) Rdst = (k == 3) ? (blk ? blk + map.boff[map.index[modes[1]][sk]] * esz : nullptr) : ar.take<char>(M * Q * esz);
+    nd.nred = 0;
+    auto route = [&](bool on, int64_t copies, int64_t n, void* dst, void*& kernel_out) {
+        if (!on) {
+            kernel_out = nullptr;
+            return;
+        }
+        if (copies <= 1) {
+            kernel_out = dst;
+            return;
+        }
+        void* part = ar.take<char>(copies * n * esz);
+        kernel_out = part;
+        nd.red.src[nd.nred] = part;
+        nd.red.dst[nd.nred] = dst;
+        nd.red.n[nd.nred] = n;
+        nd.red.K[nd.nred] = (int)copies;
+        ++nd.nred;
+    };
+    route(a.doL, nd.sh.nq, P * M, Ldst, a.L);
+    route(a.doR, nd.sh.npt, M * Q, Rdst, a.R);
+    route(a.doC, nd.sh.nmt, P * Q, Cdst, a.C);
+    nodes_.push_back(nd);
+    shapes.push_back(nd.sh);
+    const int accfmt = f64 ? HOSCF_F64 : HOSCF_F32;
+    if (a.doL && k - 1 >= 3) add_node(accfmt, Ldst, modes, k - 1, 1.f, needL, ar, tune);
+    if (a.doR && k - 1 >= 3) add_node(accfmt, Rdst, modes + 1, k - 1, 1.f, needR, ar, tune);
+}
+
+bool SweepPlan::build(const hoscf_tensor& T, int fmt, const void* data, float scale, void* blocks_out,
+                      Arena& ar, const SweepTuning& tune) {
+    map.init(T.order, T.dims);
+    f64 = (fmt == HOSCF_F64);
+    root_fmt_ = fmt;
+    root_data_ = data;
+    root_scale_ = scale;
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    xu = ar.take<double>(map.D);
+    xa = ar.take<char>(map.D * esz);
+    blocks = blocks_out ? blocks_out : ar.take<char>(map.total() * esz);
+    blocksT = ar.take<char>(map.total() * esz);
+    tr_.nblk = map.nblk;
+    tr_.tiles_first[0] = 0;
+    for (int b = 0; b < map.nblk; ++b) {
+        tr_.rows[b] = map.dims[map.bm[b]];
+        tr_.cols[b] = map.dims[map.bn[b]];
+        tr_.off[b] = map.boff[b];
+        tr_.tiles_first[b + 1] = tr_.tiles_first[b] + ((tr_.rows[b] + 31) / 32) * ((tr_.cols[b] + 31) / 32);
+    }
+    nodes_.clear();
+    shapes.clear();
+    static const int esz_fmt[4] = {8, 4, 2, 1};
+    int64_t n = 1;
+    for (int i = 0; i < T.order; ++i) n *= T.dims[i];
+    bytes_read = n * esz_fmt[fmt];
+    order2_ = (T.order == 2);
+    if (!order2_) {
+        int modes[kMaxOrder];
+        for (int i = 0; i < T.order; ++i) modes[i] = i;
+        const uint32_t all = (map.nblk >= 32) ? 0xffffffffu : ((1u << map.nblk) - 1u);
+        add_node(fmt, data, modes, T.order, scale, all, ar, tune);
+    }
+    return ar.ok;
+}
+
+hipError_t SweepPlan::run(const double* x, SolveState* st, hipStream_t s, hipEvent_t* ev_k1) const {
+    FactorOffsets off;
+    for (int i = 0; i <= map.N; ++i) off.off[i] = map.xoff[i];
+    hipError_t e = launch_prep(f64, x, map.N, off, xu, xa, st, s);
+    if (e != hipSuccess) return e;
+    if (order2_) {
+        e = launch_convert(root_fmt_, root_data_, map.dims[0] * map.dims[1], root_scale_, f64, blocks, s);
+        if (e != hipSuccess) return e;
+        return launch_transpose(f64, blocks, tr_, blocksT, s);
+    }
+    int idx = 0;
+    for (const Node& nd : nodes_) {
+        if (nd.kron) {
+            e = launch_kron(f64, xu, nd.k, nd.w, s);
+            if (e != hipSuccess) return e;
+        }
+        if (ev_k1) {
+            e = hipEventRecord(ev_k1[2 * idx], s);
+            if (e != hipSuccess) return e;
+        }
+        e = launch_ttvc3(nd.fmt, nd.sh, nd.a, s);
+        if (e != hipSuccess) return e;
+        if (ev_k1) {
+            e = hipEventRecord(ev_k1[2 * idx + 1], s);
+            if (e != hipSuccess) return e;
+        }
+        ++idx;
+        e = launch_reduce(f64, nd.red, nd.nred, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_transpose(f64, blocks, tr_, blocksT, s);
+}
+
+}  // namespace hoscf

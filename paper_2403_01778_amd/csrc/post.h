@@ -1,0 +1,53 @@
+// Host-side interface of the post-sweep cooperative kernel.
+#pragma once
+
+#include "common.h"
+
+namespace hoscf {
+
+constexpr int kKmaxLds = 256;  // largest Lanczos dimension held in LDS
+constexpr int kVecLds = 8192;  // vectors up to this length are staged in LDS for the J products
+
+enum PostMode { kPostEpilogue = 0, kPostEigen = 1, kPostRqi = 2 };
+
+struct PostArgs {
+    const void* blocks;
+    void* blocksT;   // [total] transposed copies of the blocks (written by the sweep)
+    int N;
+    int64_t D;
+    int nblk;
+    int64_t dims[kMaxOrder];
+    int64_t xoff[kMaxOrder + 1];
+    int bm[kMaxBlocks], bn[kMaxBlocks];
+    int64_t boff[kMaxBlocks];
+    // row i of J's block-row n, block-column m: row i of A_{n,m} (n < m) or of A_{m,n}' (n > m)
+    int64_t seg_base[kMaxOrder][kMaxOrder];
+    int seg_src[kMaxOrder][kMaxOrder];  // 0 = blocks, 1 = blocksT
+    int mode;
+    double tol, eig_tol, solve_tol;
+    int kmax;
+    int canonical;
+    int nwg;
+    int RK;
+    double* x;       // [D] unit factors in; new iterate out (eigen / accepted Rayleigh step)
+    double* g;       // [D] mode vectors out
+    SolveState* st;
+    unsigned* bar;   // grid barrier words (inside st)
+    double* scalars_out;
+    double* V;       // [(kmax+1) * D] Lanczos basis
+    double* w;       // [D]
+    double* red;     // [2][nwg][RK]
+};
+
+class PostPlan {
+   public:
+    bool build(const BlockMap& map, bool f64_blocks, int kmax, int max_wg, Arena& ar);
+    hipError_t run(int mode, const void* blocks, const void* blocksT, double* x, double* g, SolveState* st, double* scalars,
+                   double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s) const;
+    PostArgs a{};
+    bool f64 = false;
+};
+
+int post_max_workgroups(bool f64);
+
+}  // namespace hoscf

@@ -1,0 +1,842 @@
+// Post-sweep work of one HOSCF / iHOSCF iteration in a single launch
+// (cooperative when it spans several workgroups):
+//   A. mode vectors g = J(x) x (times N-1), sigma, ||J||_F and the residual of
+//      the stopping test (eq. stop-3 read as the NEPv residual at the
+//      iterate, with J(x~)x~ = [g_n]/sqrt(N) and rho = sigma);
+//   B. Lanczos with full (twice-applied) reorthogonalisation on J = [blocks] /
+//      (N-1), started at x~ = [u_n]/sqrt(N) (Alg. 1, eigen-step), giving
+//      either the largest-magnitude Ritz pair (HOSCF) or the Galerkin solution
+//      of (J - rho I) z = x~ with rho = x~'J x~ (the Rayleigh step of
+//      Section 4.4);
+//   C. block normalisation (eq. factor), the sign representative, and the
+//      acceptance test of the Rayleigh step.
+// The Krylov vectors and all reductions are FP64; the blocks are read in their
+// stored type (FP32 or FP64).  Each workgroup owns a range of the D rows of J;
+// a row of J is the concatenation of rows of the stored blocks and of their
+// transposes (written once per launch), so a workgroup forms its rows of J v
+// without partial sums.  Inner products are combined across workgroups in a
+// fixed order, so the result does not depend on timing.
+#include <algorithm>
+
+#include "common.h"
+#include "post.h"
+
+namespace hoscf {
+
+constexpr int BS = 256;  // threads per workgroup
+constexpr int RW = 8;    // J rows a wave reduces together
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k);
+    return v;
+}
+
+// Sum over the workgroup (256 threads); every thread receives the total.
+__device__ double wg_sum(double v, double* lds4) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double t = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+    __syncthreads();
+    return t;
+}
+
+// Transposed butterfly (see the TTVc kernel): N values per lane summed over
+// the 64 lanes; on return lane-local value j is the total of index base + j.
+template <int N, int STEPS>
+__device__ __forceinline__ void xred64(double* v, int lane, int& base) {
+    if constexpr (STEPS > 0) {
+        constexpr int mask = 1 << (STEPS - 1);
+        if constexpr (N > 1) {
+            constexpr int H = N / 2;
+            const bool up = (lane & mask) != 0;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                double send = up ? v[j] : v[j + H];
+                double keep = up ? v[j + H] : v[j];
+                v[j] = keep + __shfl_xor(send, mask);
+            }
+            base += up ? H : 0;
+            xred64<H, STEPS - 1>(v, lane, base);
+        } else {
+            v[0] += __shfl_xor(v[0], mask);
+            xred64<1, STEPS - 1>(v, lane, base);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric tridiagonal helpers (Lanczos matrix T_m: diag al, off-diag be).
+// ---------------------------------------------------------------------------
+
+// Number of eigenvalues of T_m smaller than x (Sturm sequence of the LDL'
+// pivots).
+__device__ int sturm_count(const double* al, const double* b2, int m, double x, double pivmin) {
+    int cnt = 0;
+    double d = al[0] - x;
+    if (fabs(d) < pivmin) d = -pivmin;
+    cnt += d < 0.0;
+    for (int k = 1; k < m; ++k) {
+        d = (al[k] - x) - b2[k - 1] / d;
+        if (fabs(d) < pivmin) d = -pivmin;
+        cnt += d < 0.0;
+    }
+    return cnt;
+}
+
+// Extreme eigenvalues of T_m by 32-way multisection per end (wave 0 only;
+// lanes 0-31 bracket the smallest, lanes 32-63 the largest).
+__device__ void extreme_eigs(const double* al, const double* b2, const double* be, int m, double* out_lo,
+                             double* out_hi) {
+    const int lane = threadIdx.x & 63;
+    double glo = 1e300, ghi = -1e300, bmax = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double r = (k > 0 ? fabs(be[k - 1]) : 0.0) + (k < m - 1 ? fabs(be[k]) : 0.0);
+        glo = fmin(glo, al[k] - r);
+        ghi = fmax(ghi, al[k] + r);
+        if (k < m - 1) bmax = fmax(bmax, b2[k]);
+    }
+    const double scale = fmax(fabs(glo), fabs(ghi));
+    const double pivmin = 1e-290 * fmax(1.0, bmax);
+    const double pad = 2.0 * 2.220446049250313e-16 * scale + pivmin;
+    double lo0 = glo - pad, hi0 = ghi + pad;  // interval for the smallest eigenvalue
+    double lo1 = glo - pad, hi1 = ghi + pad;  // interval for the largest
+    const bool low_half = lane < 32;
+    const int sub = lane & 31;
+    for (int round = 0; round < 14; ++round) {
+        const double lo = low_half ? lo0 : lo1, hi = low_half ? hi0 : hi1;
+        const double x = lo + (hi - lo) * (double)(sub + 1) / 33.0;
+        const int c = sturm_count(al, b2, m, x, pivmin);
+        // smallest: first point with count >= 1; largest: first point with count == m
+        const bool hit = low_half ? (c >= 1) : (c >= m);
+        const unsigned long long bal = __ballot(hit);
+        const unsigned lo_bits = (unsigned)(bal & 0xffffffffull);
+        const unsigned hi_bits = (unsigned)(bal >> 32);
+        // lane-uniform update of both intervals
+        const double xs_lo_step = (hi0 - lo0) / 33.0;
+        const double xs_hi_step = (hi1 - lo1) / 33.0;
+        if (lo_bits) {
+            const int f = __ffs(lo_bits) - 1;
+            const double nhi = lo0 + xs_lo_step * (f + 1);
+            const double nlo = f > 0 ? lo0 + xs_lo_step * f : lo0;
+            lo0 = nlo;
+            hi0 = nhi;
+        } else {
+            lo0 = lo0 + xs_lo_step * 32;
+        }
+        if (hi_bits) {
+            const int f = __ffs(hi_bits) - 1;
+            const double nhi = lo1 + xs_hi_step * (f + 1);
+            const double nlo = f > 0 ? lo1 + xs_hi_step * f : lo1;
+            lo1 = nlo;
+            hi1 = nhi;
+        } else {
+            lo1 = lo1 + xs_hi_step * 32;
+        }
+        const double tol = 4.0 * 2.220446049250313e-16 * scale + pivmin;
+        if (hi0 - lo0 <= tol && hi1 - lo1 <= tol) break;
+    }
+    *out_lo = 0.5 * (lo0 + hi0);
+    *out_hi = 0.5 * (lo1 + hi1);
+}
+
+// Solve (T_m - shift I) y = rhs by Gaussian elimination with partial
+// pivoting on the tridiagonal (single thread).  Zero pivots are replaced by
+// `zrep` when zrep > 0; otherwise the call reports singularity (returns false).
+__device__ bool tri_solve(const double* al, const double* be, int m, double shift, double* y, double zrep,
+                          double* d, double* du, double* du2, double* dl) {
+    for (int i = 0; i < m; ++i) {
+        d[i] = al[i] - shift;
+        if (i < m - 1) {
+            du[i] = be[i];
+            dl[i] = be[i];
+            du2[i] = 0.0;
+        }
+    }
+    for (int i = 0; i < m - 1; ++i) {
+        if (fabs(d[i]) >= fabs(dl[i])) {
+            if (d[i] == 0.0) {
+                if (zrep <= 0.0) return false;
+                d[i] = zrep;
+            }
+            const double f = dl[i] / d[i];
+            d[i + 1] -= f * du[i];
+            y[i + 1] -= f * y[i];
+        } else {
+            const double f = d[i] / dl[i];
+            d[i] = dl[i];
+            const double t = du[i];
+            du[i] = d[i + 1];
+            d[i + 1] = t - f * d[i + 1];
+            if (i < m - 2) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du[i + 1];
+            }
+            const double yt = y[i];
+            y[i] = y[i + 1];
+            y[i + 1] = yt - f * y[i + 1];
+        }
+    }
+    if (d[m - 1] == 0.0) {
+        if (zrep <= 0.0) return false;
+        d[m - 1] = zrep;
+    }
+    y[m - 1] /= d[m - 1];
+    if (m >= 2) y[m - 2] = (y[m - 2] - du[m - 2] * y[m - 1]) / d[m - 2];
+    for (int i = m - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / d[i];
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Grid-wide barrier for a co-resident grid (cooperative launch).  Arrival is a
+// device-scope atomic add; the last arrival advances the generation word.
+// Waiting is bounded: after ~2^26 polls the barrier gives up and raises
+// `timeout` so the kernel still runs to its end.
+// ---------------------------------------------------------------------------
+__device__ void grid_barrier(unsigned* bar, unsigned nwg, int* timeout) {
+    __syncthreads();
+    if (nwg == 1) return;
+    if (threadIdx.x == 0) {
+        unsigned* count = bar;
+        unsigned* gen = bar + 1;
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // release: this workgroup's stores are visible before its arrival is
+        const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nwg - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned polls = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (++polls > (1u << 28)) {
+                    *timeout = 1;
+                    break;
+                }
+            }
+        }
+        // acquire once after the wait: later loads see every arrival's stores
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+struct Lds {
+    double al[kKmaxLds], be[kKmaxLds], b2[kKmaxLds];
+    double s[kKmaxLds];       // Ritz vector / Galerkin solution of T_m
+    double hsum[kKmaxLds + 4 * kMaxOrder + 8];
+    double mine[kKmaxLds + 4 * kMaxOrder + 8];
+    double tri[4 * kKmaxLds]; // tridiagonal solve scratch
+    double red4[BS / 64];
+    double part[BS];
+    int64_t xoff[kMaxOrder + 1];
+    double theta, ritz;
+    int stop, ok, timeout;
+};
+
+// All-reduce of K per-workgroup partials held in L.mine (alternating
+// buffers, so a fast workgroup never overwrites partials another is still
+// summing).  Totals land in L.hsum.
+__device__ void allreduce(const PostArgs& a, int K, int& parity, Lds& L) {
+    if (a.nwg == 1) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += BS) L.hsum[k] = L.mine[k];
+        __syncthreads();
+        return;
+    }
+    double* buf = a.red + (size_t)parity * a.nwg * a.RK;
+    parity ^= 1;
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += BS) buf[(size_t)blockIdx.x * a.RK + k] = L.mine[k];
+    grid_barrier(a.bar, a.nwg, &L.timeout);
+    for (int k = threadIdx.x; k < K; k += BS) {
+        // eight independent chains (fixed assignment w mod 8), combined pairwise
+        double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int w = 0;
+        for (; w + 8 <= a.nwg; w += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s8[u] += buf[(size_t)(w + u) * a.RK + k];
+        }
+        if (w < a.nwg) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int wu = w + u < a.nwg ? w + u : 0;
+                const double t = buf[(size_t)wu * a.RK + k];
+                s8[u] += (w + u < a.nwg) ? t : 0.0;
+            }
+        }
+        L.hsum[k] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    }
+    __syncthreads();
+}
+
+// Per-thread partial dot products of own rows, summed over the workgroup
+// into L.mine[k].
+__device__ void wg_to_mine(double v, int k, Lds& L) {
+    v = wg_sum(v, L.red4);
+    if (threadIdx.x == 0) L.mine[k] = v;
+}
+
+// Copy n doubles from global memory into LDS with eight loads per thread in
+// flight (indices clamped, stores masked).
+__device__ void stage_to_lds(double* dst, const double* src, int64_t n) {
+    for (int64_t b = threadIdx.x; b < n; b += 8 * BS) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = b + (int64_t)u * BS;
+            t[u] = src[i < n ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = b + (int64_t)u * BS;
+            if (i < n) dst[i] = t[u];
+        }
+    }
+}
+
+// Raw (N-1) J v for the workgroup's own rows, written to out[r]; returns the
+// thread's share of the sum over own rows of ||row||^2 when want_fro.  v is
+// staged in LDS when it fits; each lane keeps RW rows x 4 loads in flight.
+template <typename B>
+__device__ double matvec_rows(const PostArgs& a, const double* v, double* out, double scale, bool want_fro,
+                              int64_t r_lo, int64_t r_hi, double* vlds) {
+    const B* blocks = static_cast<const B*>(a.blocks);
+    const B* bt = static_cast<const B*>(a.blocksT);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar table reads
+    const bool staged = a.D <= kVecLds;
+    if (staged) {
+        stage_to_lds(vlds, v, a.D);
+        __syncthreads();
+    }
+    const double* vv = staged ? vlds : v;
+    double fro = 0.0;
+    for (int64_t r0 = r_lo + (int64_t)wave * RW; r0 < r_hi; r0 += (int64_t)(BS / 64) * RW) {
+        double acc[RW];
+        int nk[RW];
+        int64_t ik[RW];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            acc[k] = 0.0;
+            const int64_t r = r0 + k < r_hi ? r0 + k : r_hi - 1;  // clamped: always a valid row
+            int n = 0;
+            while (r >= a.xoff[n + 1]) ++n;
+            nk[k] = n;
+            ik[k] = r - a.xoff[n];
+        }
+        for (int sidx = 0; sidx < a.N - 1; ++sidx) {
+            const B* rowp[RW];
+            const double* vm[RW];
+            int64_t len[RW];
+            int64_t lmax = 0;
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int n = nk[k];
+                const int m = sidx < n ? sidx : sidx + 1;  // the sidx-th mode other than n
+                len[k] = (r0 + k < r_hi) ? a.dims[m] : 0;
+                rowp[k] = (a.seg_src[n][m] ? bt : blocks) + a.seg_base[n][m] + ik[k] * a.dims[m];
+                vm[k] = vv + a.xoff[m];
+                lmax = len[k] > lmax ? len[k] : lmax;
+            }
+            for (int64_t j0 = lane; j0 < lmax; j0 += 256) {
+                // every load is issued unconditionally at a clamped, valid index
+                // (index 0 of the same row) and masked afterwards, so all
+                // RW x 4 loads of a lane are in flight together
+                double val[RW][4];
+#pragma unroll
+                for (int k = 0; k < RW; ++k)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t j = j0 + 64 * u;
+                        const int64_t jc = j < len[k] ? j : 0;
+                        const double raw = (double)rowp[k][jc];
+                        val[k][u] = j < len[k] ? raw : 0.0;
+                    }
+#pragma unroll
+                for (int k = 0; k < RW; ++k)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t j = j0 + 64 * u;
+                        const int64_t jc = j < len[k] ? j : 0;
+                        acc[k] = fma(val[k][u], vm[k][jc], acc[k]);
+                        if (want_fro) fro = fma(val[k][u], val[k][u], fro);
+                    }
+            }
+        }
+        int base = 0;
+        xred64<RW, 6>(acc, lane, base);
+        if ((lane & 7) == 0) {
+            const int64_t r = r0 + base;
+            if (r < r_hi) out[r] = acc[0] * scale;
+        }
+    }
+    return fro;
+}
+
+// h_i = sum over own rows of V_i[r] w[r] for i <= j into mine[i].  Wave
+// `wave` takes basis vectors i = wave + 4u (u < 8) per round, lanes stride
+// over the own rows; the eight loads per lane are independent.
+__device__ void own_dots(const double* V, const double* w, int64_t D, int j, int64_t r_lo, int64_t r_hi,
+                         double* mine) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int NW = BS / 64;
+    for (int i0 = wave; i0 <= j; i0 += 8 * NW) {
+        double h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h[u] = 0.0;
+        for (int64_t r = r_lo + lane; r < r_hi; r += 64) {
+            const double wr = w[r];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * NW;
+                const int ic = i <= j ? i : 0;
+                const double vi = V[(size_t)ic * D + r];
+                h[u] = fma(i <= j ? vi : 0.0, wr, h[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double t = wave_sum(h[u]);
+            const int i = i0 + u * NW;
+            if (lane == 0 && i <= j) mine[i] = t;
+        }
+    }
+}
+
+// out[r] = sum_{i<m} c_i V_i[r] over own rows: the four waves take interleaved
+// quarters of i (eight independent loads per lane per round), partial sums
+// meet in LDS in a fixed order.  Returns through `out` (may alias nothing read).
+__device__ void own_combine(const double* V, int64_t D, int m, int64_t r_lo, int64_t r_hi, const double* c,
+                            double* part /* LDS [NW][64] */, double* out, bool subtract) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int NW = BS / 64;
+    for (int64_t rb = r_lo; rb < r_hi; rb += 64) {
+        const int64_t r = rb + lane;
+        const int64_t rc = r < r_hi ? r : r_lo;
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+        for (int i0 = wave * 8; i0 < m; i0 += 8 * NW) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u;
+                const int ic = i < m ? i : 0;
+                const double vi = V[(size_t)ic * D + rc];
+                acc[u] = fma(i < m ? c[ic] : 0.0, vi, acc[u]);
+            }
+        }
+        part[wave * 64 + lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        __syncthreads();
+        if (wave == 0 && r < r_hi) {
+            double t = part[lane];
+            for (int k = 1; k < NW; ++k) t += part[k * 64 + lane];
+            out[r] = subtract ? out[r] - t : t;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename B>
+__global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
+    __shared__ Lds L;
+    __shared__ double vlds[kVecLds];
+    const int tid = threadIdx.x;
+    const int64_t D = a.D;
+    const int64_t r_lo = D * blockIdx.x / a.nwg, r_hi = D * (blockIdx.x + 1) / a.nwg;
+    const double inv_n1 = 1.0 / (double)(a.N - 1);
+    const double inv_sqrtN = 1.0 / sqrt((double)a.N);
+    int parity = 0;
+    if (tid == 0) L.timeout = 0;
+    if (tid <= a.N) L.xoff[tid] = a.xoff[tid];
+    __syncthreads();
+    const bool tr = blockIdx.x == 0 && tid == 0;
+    uint64_t* trace = a.st->trace + (a.mode == kPostEpilogue ? 0 : 10);
+#define HOSCF_MARK(k) \
+    if (tr) trace[k] = __builtin_amdgcn_s_memrealtime()
+    HOSCF_MARK(0);
+
+    // ---- A. g, sigma, ||J||_F, residual -------------------------------------
+    double fro = matvec_rows<B>(a, a.x, a.g, inv_n1, true, r_lo, r_hi, vlds);
+    __syncthreads();
+    HOSCF_MARK(1);
+    double s0 = 0.0;  // u_1' g_1 over own rows of block 1
+    for (int64_t r = r_lo + tid; r < r_hi && r < L.xoff[1]; r += BS) s0 = fma(a.x[r], a.g[r], s0);
+    wg_to_mine(s0, 0, L);
+    wg_to_mine(fro, 1, L);
+    allreduce(a, 2, parity, L);
+    HOSCF_MARK(2);
+    const double sigma = L.hsum[0];
+    const double normJ = sqrt(L.hsum[1]) * inv_n1;
+    double rr = 0.0;
+    for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
+        const double e = a.g[r] - sigma * a.x[r];
+        rr = fma(e, e, rr);
+    }
+    wg_to_mine(rr, 0, L);
+    allreduce(a, 1, parity, L);
+    HOSCF_MARK(3);
+    const double den = normJ + fabs(sigma);
+    const bool zero = !(den > 0.0);  // J = 0: T vanishes on the current factors
+    const double res = zero ? INFINITY : sqrt(L.hsum[0] / (double)a.N) / den;
+    const bool nonfinite = !isfinite(sigma) || !isfinite(normJ) || (!zero && !isfinite(res));
+    if (blockIdx.x == 0 && tid == 0) {
+        a.st->sigma = sigma;
+        a.st->res = res;
+        a.st->normJ = normJ;
+        a.st->converged = (res <= a.tol) ? 1 : 0;
+        a.st->accepted = 0;
+        a.st->lanczos = 0;
+        a.st->eig_unconverged = 0;
+        if (nonfinite) a.st->nonfinite = 1;
+        if (zero) a.st->degenerate = 1;
+        if (a.scalars_out) {
+            a.scalars_out[0] = sigma;
+            a.scalars_out[1] = res;
+            a.scalars_out[2] = normJ;
+            a.scalars_out[3] = nonfinite ? 1.0 : 0.0;
+        }
+    }
+    bool done = a.mode == kPostEpilogue || nonfinite || zero || (a.mode == kPostEigen && res <= a.tol);
+
+    // ---- B. Lanczos from x~ --------------------------------------------------
+    const int kmax = a.kmax;
+    double* V = a.V;
+    double* w = a.w;
+    int m = 0;
+    double rho = 0.0;
+    if (!done) {
+        for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
+            V[r] = a.x[r] * inv_sqrtN;
+            w[r] = a.g[r] * inv_sqrtN;  // J x~ = [g_n] / sqrt(N)
+        }
+        grid_barrier(a.bar, a.nwg, &L.timeout);  // V_0 complete before any matvec reads it
+        bool stop = false;
+        for (int j = 0; j < kmax && !stop; ++j) {
+            if (j > 0) {
+                matvec_rows<B>(a, V + (size_t)j * D, w, inv_n1, false, r_lo, r_hi, vlds);
+                __syncthreads();
+                if (j == 1) HOSCF_MARK(5);
+            }
+            // pass 1: h_i = V_i . w over own rows
+            own_dots(V, w, D, j, r_lo, r_hi, L.mine);
+            allreduce(a, j + 1, parity, L);
+            own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+            if (tid == 0) L.al[j] = L.hsum[j];
+            __syncthreads();
+            // pass 2: h'_i and ||w||^2
+            own_dots(V, w, D, j, r_lo, r_hi, L.mine);
+            double nn = 0.0;
+            for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
+            nn = wg_sum(nn, L.red4);
+            if (tid == 0) L.mine[j + 1] = nn;
+            allreduce(a, j + 2, parity, L);
+            double corr2 = 0.0;
+            for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
+            const double beta = sqrt(fmax(L.hsum[j + 1] - corr2, 0.0));
+            own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+            if (tid == 0) {
+                L.al[j] += L.hsum[j];
+                L.be[j] = beta;
+                L.b2[j] = beta * beta;
+            }
+            __syncthreads();
+            m = j + 1;
+            rho = L.al[0];
+            const bool invariant = beta <= 1e-14 * normJ;
+            const bool check = invariant || m == kmax || m <= 8 || (m % 4) == 0;
+            if (check) {
+                // every workgroup takes the same decision from the same numbers
+                if (a.mode == kPostEigen) {
+                    if (tid < 64) {
+                        double lmin = 0.0, lmax = 0.0;
+                        if (m == 1) {
+                            lmin = lmax = L.al[0];
+                        } else {
+                            extreme_eigs(L.al, L.b2, L.be, m, &lmin, &lmax);
+                        }
+                        if (tid == 0) {
+                            const double th = (fabs(lmin) > fabs(lmax) * (1.0 + 1e-12)) ? lmin : lmax;
+                            double* sv = L.s;
+                            for (int i = 0; i < m; ++i) sv[i] = 1.0;
+                            const double zrep = 2.220446049250313e-16 * fmax(fabs(lmin), fabs(lmax)) + 1e-300;
+                            for (int it = 0; it < 3; ++it) {
+                                tri_solve(L.al, L.be, m, th, sv, zrep, L.tri, L.tri + kKmaxLds, L.tri + 2 * kKmaxLds,
+                                          L.tri + 3 * kKmaxLds);
+                                double nrm = 0.0;
+                                for (int i = 0; i < m; ++i) nrm = fma(sv[i], sv[i], nrm);
+                                nrm = sqrt(nrm);
+                                for (int i = 0; i < m; ++i) sv[i] /= nrm;
+                            }
+                            L.theta = th;
+                            L.ritz = beta * fabs(sv[m - 1]);
+                            L.stop = (L.ritz <= a.eig_tol * fmax(normJ, fabs(th))) || invariant || m == kmax;
+                        }
+                    }
+                } else if (tid == 0) {
+                    double* t = L.s;
+                    for (int i = 0; i < m; ++i) t[i] = 0.0;
+                    t[0] = 1.0;
+                    bool ok = m >= 2 && tri_solve(L.al, L.be, m, rho, t, 0.0, L.tri, L.tri + kKmaxLds,
+                                                  L.tri + 2 * kKmaxLds, L.tri + 3 * kKmaxLds);
+                    double tn = 0.0;
+                    if (ok)
+                        for (int i = 0; i < m; ++i) tn = fma(t[i], t[i], tn);
+                    ok = ok && isfinite(tn) && tn > 0.0;
+                    L.ok = ok;
+                    // Galerkin residual ||x~ - (J - rho I) z_m|| = beta_m |t_m| against ||x~|| = 1:
+                    // small in absolute terms means z_m is the solve's answer, not merely a
+                    // near-null vector of J - rho I.
+                    L.ritz = ok ? beta * fabs(t[m - 1]) : INFINITY;
+                    L.stop = (m >= 2 && ok && L.ritz <= a.solve_tol) || invariant || m == kmax;
+                }
+                __syncthreads();
+                stop = L.stop != 0;
+            }
+            if (!stop) {
+                const double ib = 1.0 / beta;
+                double* Vn = V + (size_t)(j + 1) * D;
+                for (int64_t r = r_lo + tid; r < r_hi; r += BS) Vn[r] = w[r] * ib;
+                grid_barrier(a.bar, a.nwg, &L.timeout);
+            }
+            if (j == 0) HOSCF_MARK(4);
+            if (j == 1) HOSCF_MARK(6);
+        }
+        HOSCF_MARK(7);
+    }
+
+    // ---- C. the new iterate ---------------------------------------------------
+    bool accept = !done;
+    if (!done && a.mode == kPostRqi) {
+        const bool ok = L.ok != 0;
+        if (ok && tid == 0) {
+            const double* t = L.s;
+            double num = 0.0, den2 = 0.0;
+            for (int i = 0; i < m; ++i) {
+                double Tt = L.al[i] * t[i];
+                if (i > 0) Tt = fma(L.be[i - 1], t[i - 1], Tt);
+                if (i < m - 1) Tt = fma(L.be[i], t[i + 1], Tt);
+                num = fma(t[i], Tt, num);
+                den2 = fma(t[i], t[i], den2);
+            }
+            L.theta = num / den2;
+        }
+        __syncthreads();
+        accept = ok && fabs(L.theta) > fabs(rho);
+    }
+    if (!done && blockIdx.x == 0 && tid == 0) {
+        a.st->lanczos = m;
+        a.st->rho = rho;
+        a.st->theta = L.theta;
+        a.st->ritz_res = L.ritz;
+        if (a.mode == kPostEigen) a.st->eig_unconverged = (L.ritz > a.eig_tol * fmax(normJ, fabs(L.theta))) ? 1 : 0;
+    }
+    if (accept) {
+        // y = V_m s (own rows), then per-block norm and largest-|entry|
+        const int N = a.N;
+        double nrm2[kMaxOrder], best[kMaxOrder], bval[kMaxOrder];
+        int64_t bidx[kMaxOrder];
+        for (int n = 0; n < N; ++n) {
+            nrm2[n] = 0.0;
+            best[n] = -1.0;
+            bval[n] = 0.0;
+            bidx[n] = INT64_MAX;
+        }
+        own_combine(V, D, m, r_lo, r_hi, L.s, L.part, w, false);
+        for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
+            const double y = w[r];
+            int n = 0;
+            while (r >= L.xoff[n + 1]) ++n;
+            nrm2[n] = fma(y, y, nrm2[n]);
+            const double ay = fabs(y);
+            if (ay > best[n]) {  // a thread visits rows in increasing order: first max wins
+                best[n] = ay;
+                bval[n] = y;
+                bidx[n] = r;
+            }
+        }
+        __shared__ double wbv[BS / 64], wbs[BS / 64];
+        __shared__ int64_t wbi[BS / 64];
+        for (int n = 0; n < N; ++n) {
+            const double sn = wg_sum(nrm2[n], L.red4);
+            double bv = best[n];
+            int64_t bi = bidx[n];
+            double bs = bval[n];
+            for (int k = 32; k >= 1; k >>= 1) {
+                const double ov = __shfl_xor(bv, k);
+                const int64_t oi = __shfl_xor(bi, k);
+                const double os = __shfl_xor(bs, k);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                    bs = os;
+                }
+            }
+            if ((tid & 63) == 0) {
+                wbv[tid >> 6] = bv;
+                wbi[tid >> 6] = bi;
+                wbs[tid >> 6] = bs;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double v = wbv[0];
+                int64_t ix = wbi[0];
+                double sg = wbs[0];
+                for (int k = 1; k < BS / 64; ++k)
+                    if (wbv[k] > v || (wbv[k] == v && wbi[k] < ix)) {
+                        v = wbv[k];
+                        ix = wbi[k];
+                        sg = wbs[k];
+                    }
+                L.mine[4 * n + 0] = sn;
+                L.mine[4 * n + 1] = v;
+                L.mine[4 * n + 2] = (double)ix;
+                L.mine[4 * n + 3] = sg;
+            }
+            __syncthreads();
+        }
+        // combine over workgroups in workgroup order
+        if (a.nwg == 1) {
+            if (tid == 0)
+                for (int n = 0; n < N; ++n) {
+                    L.hsum[2 * n] = L.mine[4 * n];
+                    L.hsum[2 * n + 1] = L.mine[4 * n + 3];
+                }
+            __syncthreads();
+        } else {
+            double* buf = a.red + (size_t)parity * a.nwg * a.RK;
+            parity ^= 1;
+            for (int k = tid; k < 4 * N; k += BS) buf[(size_t)blockIdx.x * a.RK + k] = L.mine[k];
+            grid_barrier(a.bar, a.nwg, &L.timeout);
+            if (tid == 0) {
+                for (int n = 0; n < N; ++n) {
+                    double sn = 0.0, v = -1.0, sg = 0.0, ix = 1e300;
+                    for (int wg = 0; wg < a.nwg; ++wg) {
+                        const double* p = buf + (size_t)wg * a.RK + 4 * n;
+                        sn += p[0];
+                        if (p[1] > v || (p[1] == v && p[2] < ix)) {
+                            v = p[1];
+                            ix = p[2];
+                            sg = p[3];
+                        }
+                    }
+                    L.hsum[2 * n] = sn;
+                    L.hsum[2 * n + 1] = sg;
+                }
+            }
+            __syncthreads();
+        }
+        double fl[kMaxOrder], inv[kMaxOrder];
+        bool degenerate = false;
+        double f0 = 1.0;
+        for (int n = 0; n < N; ++n) {
+            const double sn = L.hsum[2 * n];
+            if (!(sn > 0.0)) degenerate = true;
+            inv[n] = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;
+            fl[n] = 1.0;
+            if (a.canonical && n >= 1 && L.hsum[2 * n + 1] < 0.0) {
+                fl[n] = -1.0;
+                f0 = -f0;
+            }
+        }
+        fl[0] = f0;
+        if (degenerate) {
+            if (blockIdx.x == 0 && tid == 0) a.st->degenerate = 1;
+        } else {
+            for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
+                int n = 0;
+                while (r >= L.xoff[n + 1]) ++n;
+                a.x[r] = fl[n] * w[r] * inv[n];
+            }
+            if (blockIdx.x == 0 && tid == 0 && a.mode == kPostRqi) a.st->accepted = 1;
+        }
+    }
+    if (tid == 0 && L.timeout) a.st->barrier_timeout = 1;
+    HOSCF_MARK(8);
+    if (tr) trace[9] = (uint64_t)m;
+#undef HOSCF_MARK
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+bool PostPlan::build(const BlockMap& map, bool f64_blocks, int kmax, int max_wg, Arena& ar) {
+    a = PostArgs{};
+    f64 = f64_blocks;
+    a.N = map.N;
+    a.D = map.D;
+    a.nblk = map.nblk;
+    for (int i = 0; i < map.N; ++i) a.dims[i] = map.dims[i];
+    for (int i = 0; i <= map.N; ++i) a.xoff[i] = map.xoff[i];
+    for (int b = 0; b < map.nblk; ++b) {
+        a.bm[b] = map.bm[b];
+        a.bn[b] = map.bn[b];
+        a.boff[b] = map.boff[b];
+    }
+    for (int n = 0; n < map.N; ++n)
+        for (int m = 0; m < map.N; ++m) {
+            if (m == n) continue;
+            if (n < m) {  // row i of A_{n,m}
+                a.seg_src[n][m] = 0;
+                a.seg_base[n][m] = map.boff[map.index[n][m]];
+            } else {      // row i of A_{m,n}' (stored transposed)
+                a.seg_src[n][m] = 1;
+                a.seg_base[n][m] = map.boff[map.index[m][n]];
+            }
+        }
+    a.kmax = std::max(1, std::min<int>(kmax, std::min<int64_t>(kKmaxLds - 1, map.D)));
+    const size_t esz = f64_blocks ? 8 : 4;
+    const double jbytes = 2.0 * (double)map.total() * (double)esz;
+    int nwg = (int)std::ceil(jbytes / (256.0 * 1024.0));
+    nwg = std::max(1, std::min<int>(nwg, (int)std::max<int64_t>(1, map.D / 32)));
+    nwg = std::min(nwg, std::max(1, std::min(max_wg, 64)));
+    a.nwg = nwg;
+    a.RK = kKmaxLds + 4 * kMaxOrder + 8;
+    a.V = ar.take<double>((size_t)(a.kmax + 1) * map.D);
+    a.w = ar.take<double>(map.D);
+    a.red = ar.take<double>((size_t)2 * nwg * a.RK);
+    return ar.ok;
+}
+
+hipError_t PostPlan::run(int mode, const void* blocks, const void* blocksT, double* x, double* g, SolveState* st, double* scalars,
+                         double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s) const {
+    PostArgs args = a;
+    args.mode = mode;
+    args.blocks = blocks;
+    args.blocksT = const_cast<void*>(blocksT);
+    args.x = x;
+    args.g = g;
+    args.st = st;
+    args.bar = st->bar;
+    args.scalars_out = scalars;
+    args.tol = tol;
+    args.eig_tol = eig_tol;
+    args.solve_tol = solve_tol;
+    args.canonical = canonical;
+    const void* fn = f64 ? reinterpret_cast<const void*>(&post_kernel<double>)
+                         : reinterpret_cast<const void*>(&post_kernel<float>);
+    if (a.nwg == 1) {
+        if (f64) hipLaunchKernelGGL(post_kernel<double>, dim3(1), dim3(BS), 0, s, args);
+        else hipLaunchKernelGGL(post_kernel<float>, dim3(1), dim3(BS), 0, s, args);
+        return hipGetLastError();
+    }
+    void* params[] = {&args};
+    return hipLaunchCooperativeKernel(fn, dim3(a.nwg), dim3(BS), params, 0, s);
+}
+
+int post_max_workgroups(bool f64) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    const void* fn = f64 ? reinterpret_cast<const void*>(&post_kernel<double>)
+                         : reinterpret_cast<const void*>(&post_kernel<float>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, BS, 0) != hipSuccess) return 1;
+    return std::max(1, cus * std::max(per, 1));
+}
+
+}  // namespace hoscf

@@ -1,0 +1,115 @@
+// Host-side interface of the TTVc sweep kernels and the sweep plan.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace hoscf {
+
+// One launch of the three-output streaming kernel over the view [P, M, Q].
+struct Ttvc3Args {
+    const void* T;            // storage-format tensor (or an FP32/FP64 intermediate)
+    int64_t P, M, Q;
+    const void* xp;           // [P] unit factor of the first mode (accumulation type)
+    const void* w;            // [M] Kronecker weight of the middle modes
+    const void* xq;           // [Q] unit factor of the last mode
+    void* L;                  // [nq][P][M]  (final when nq == 1)
+    void* R;                  // [npt][M][Q] (final when npt == 1)
+    void* C;                  // [nmt][P][Q] (final when nmt == 1)
+    int64_t BP;               // p-range of one workgroup
+    int nq;                   // q-chunks
+    int QWe;                  // width of every q-chunk (<= LR * VEC)
+    int64_t nmt;              // workgroup m-tiles
+    int doL, doR, doC;
+    float scale;              // dequantisation scale folded into every output
+};
+
+struct Ttvc3Shape {
+    int VEC = 1, LR = 64, MB = 16, QW = 64, QWe = 64;
+    int nq = 1;
+    int64_t nmt = 1, npt = 1, BP = 1;
+    int64_t grid() const { return (int64_t)nq * nmt * npt; }
+};
+
+struct ReduceJobs {
+    const void* src[3];
+    void* dst[3];
+    int64_t n[3];
+    int K[3];
+};
+
+struct FactorOffsets {
+    int64_t off[kMaxOrder + 1];
+};
+
+struct KronArgs {
+    int nmid;
+    int64_t M;
+    int64_t off[kMaxOrder];
+    int64_t dim[kMaxOrder];
+};
+
+struct TransposeArgs {
+    int nblk;
+    int64_t tiles_first[kMaxBlocks + 1];
+    int64_t rows[kMaxBlocks], cols[kMaxBlocks], off[kMaxBlocks];
+};
+
+// Tiling parameters a sweep plan uses (filled from the tile table).
+struct SweepTuning {
+    int64_t target_waves = 0;  // 0: size the grid from resident workgroups
+    int64_t bp_min = 8;
+};
+
+Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, int64_t target_waves, int64_t bp_min);
+hipError_t launch_ttvc3(int fmt, const Ttvc3Shape& sh, const Ttvc3Args& a, hipStream_t s);
+hipError_t launch_reduce(bool f64, const ReduceJobs& jobs, int njobs, hipStream_t s);
+hipError_t launch_prep(bool f64, const double* x, int N, const FactorOffsets& off, double* xu, void* xa,
+                       SolveState* st, hipStream_t s);
+hipError_t launch_kron(bool f64, const double* xu, const KronArgs& k, void* w, hipStream_t s);
+hipError_t launch_transpose(bool f64, const void* blocks, const TransposeArgs& t, void* out, hipStream_t s);
+hipError_t launch_convert(int fmt, const void* src, int64_t n, float scale, bool f64, void* dst, hipStream_t s);
+
+// The full J-build for one tensor: factor preparation, the K1 launches of the
+// order-N recursion with their partial reductions, in stream order.
+class SweepPlan {
+   public:
+    // blocks == nullptr: the blocks live in the arena.
+    bool build(const hoscf_tensor& T, int fmt, const void* data, float scale, void* blocks, Arena& ar,
+               const SweepTuning& tune);
+    // ev_k1 (optional): two events per K1 node, recorded around each launch.
+    hipError_t run(const double* x, SolveState* st, hipStream_t s, hipEvent_t* ev_k1 = nullptr) const;
+    int num_nodes() const { return (int)nodes_.size(); }
+
+    BlockMap map;
+    bool f64 = false;          // accumulation/blocks in FP64
+    void* blocks = nullptr;    // packed raw blocks
+    void* blocksT = nullptr;   // their transposes (same offsets), for row access to J
+    double* xu = nullptr;      // [D] unit factors FP64
+    void* xa = nullptr;        // [D] unit factors in the accumulation type
+    int64_t bytes_read = 0;    // algorithmic bytes of T per sweep
+    std::vector<Ttvc3Shape> shapes;  // one per K1 node (for reports)
+
+   private:
+    struct Node {
+        int fmt;
+        Ttvc3Shape sh;
+        Ttvc3Args a;
+        bool kron;
+        KronArgs k;
+        void* w;
+        ReduceJobs red;
+        int nred;
+    };
+    void add_node(int fmt, const void* in, const int* modes, int k, float scale, uint32_t need, Arena& ar,
+                  const SweepTuning& tune);
+    std::vector<Node> nodes_;
+    int root_fmt_ = 0;
+    const void* root_data_ = nullptr;
+    float root_scale_ = 1.f;
+    bool order2_ = false;
+    TransposeArgs tr_{};
+};
+
+}  // namespace hoscf

@@ -1,0 +1,556 @@
+// TTVc J-build sweep (eq. submatrix, eq. map; Section 4.2 names it the cost
+// bottleneck): every block A_{m,n} = T x_{k not in {m,n}} u_k from one
+// streaming read of T.
+//
+// The kernel works on the three-mode view T ~ [P, M, Q] = [I_first,
+// prod(middle), I_last] with the Kronecker weight w = u_mid1 (x) ... (x)
+// u_midk and produces, in one pass,
+//     L[p,m] = sum_q T[p,m,q] xq[q]     (T x_last u_last)
+//     R[m,q] = sum_p T[p,m,q] xp[p]     (T x_first u_first)
+//     C[p,q] = sum_m T[p,m,q] w[m]      (block (first, last))
+// For order 3 these are the three J blocks.  For order N the host recurses on
+// L and R (orders N-1), which are small and cache-resident.
+//
+// Layout of the work: lanes own 16-byte vectors of consecutive q (VEC
+// elements), LR lanes per row, G = 64/LR rows per wave instruction.  A wave
+// holds R for its MB rows per group in registers while it streams over a
+// p-range, flushes C once per p (the four waves of a workgroup share the
+// q-chunk and p-range and combine their C contributions in LDS, in a fixed
+// order), and reduces L per row with a transposed butterfly over its lanes.
+// Every reduction has a fixed order, so a sweep is bitwise reproducible.
+#include "common.h"
+#include "ttvc.h"
+
+#include <algorithm>
+
+namespace hoscf {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Storage formats: load VEC consecutive elements (16 bytes when VEC > 1) and
+// widen them to the accumulation type.
+// ---------------------------------------------------------------------------
+template <int FMT> struct Fmt;
+template <> struct Fmt<HOSCF_F64> { using S = double;   using A = double; static constexpr int VEC = 2; };
+template <> struct Fmt<HOSCF_F32> { using S = float;    using A = float;  static constexpr int VEC = 4; };
+template <> struct Fmt<HOSCF_BF16> { using S = uint16_t; using A = float;  static constexpr int VEC = 8; };
+template <> struct Fmt<HOSCF_FP8E4M3> { using S = uint8_t; using A = float; static constexpr int VEC = 16; };
+
+// bf16 -> f32: the bf16 bits are the high half of the binary32 encoding.
+__device__ __forceinline__ float bf16_lo(unsigned u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned u) { return __uint_as_float(u & 0xffff0000u); }
+
+// OCP E4M3 -> f32 without tables: placing the 7 magnitude bits at bit 20 of a
+// binary32 pattern gives exponent field E and mantissa m/8 (normals) or the
+// denormal m * 2^-129 (E = 0); multiplying by 2^120 rebiases (7 -> 127)
+// exactly in both cases.
+__device__ __forceinline__ float e4m3_at(unsigned byte_bits_sign31, unsigned mag_at20) {
+    return __uint_as_float(byte_bits_sign31 | mag_at20) * 0x1p120f;
+}
+__device__ __forceinline__ void e4m3x4(unsigned u, float* o) {
+    o[0] = e4m3_at((u & 0x80u) << 24, (u & 0x7fu) << 20);
+    o[1] = e4m3_at((u & 0x8000u) << 16, (u & 0x7f00u) << 12);
+    o[2] = e4m3_at((u & 0x800000u) << 8, (u & 0x7f0000u) << 4);
+    o[3] = e4m3_at(u & 0x80000000u, (u & 0x7f000000u) >> 4);
+}
+
+template <int FMT, int V> struct Loader;
+
+template <int FMT> struct Loader<FMT, 1> {
+    using S = typename Fmt<FMT>::S;
+    using A = typename Fmt<FMT>::A;
+    using Raw = S;
+    __device__ static Raw zero() { return S(0); }
+    __device__ static Raw load(const S* p) { return __builtin_nontemporal_load(p); }
+    __device__ static void cvt(Raw r, A* o) {
+        if constexpr (FMT == HOSCF_BF16) o[0] = __uint_as_float(unsigned(r) << 16);
+        else if constexpr (FMT == HOSCF_FP8E4M3) {
+            unsigned u = r;
+            o[0] = e4m3_at((u & 0x80u) << 24, (u & 0x7fu) << 20);
+        } else o[0] = A(r);
+    }
+};
+
+template <> struct Loader<HOSCF_F64, 2> {
+    using A = double;
+    using Raw = f64x2;
+    __device__ static Raw zero() { return Raw{0.0, 0.0}; }
+    __device__ static Raw load(const double* p) { return __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p)); }
+    __device__ static void cvt(Raw r, A* o) { o[0] = r.x; o[1] = r.y; }
+};
+template <> struct Loader<HOSCF_F32, 4> {
+    using A = float;
+    using Raw = f32x4;
+    __device__ static Raw zero() { return Raw{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static Raw load(const float* p) { return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p)); }
+    __device__ static void cvt(Raw r, A* o) { o[0] = r.x; o[1] = r.y; o[2] = r.z; o[3] = r.w; }
+};
+template <> struct Loader<HOSCF_BF16, 8> {
+    using A = float;
+    using Raw = u32x4;
+    __device__ static Raw zero() { return Raw{0u, 0u, 0u, 0u}; }
+    __device__ static Raw load(const uint16_t* p) { return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)); }
+    __device__ static void cvt(Raw r, A* o) {
+        o[0] = bf16_lo(r.x); o[1] = bf16_hi(r.x); o[2] = bf16_lo(r.y); o[3] = bf16_hi(r.y);
+        o[4] = bf16_lo(r.z); o[5] = bf16_hi(r.z); o[6] = bf16_lo(r.w); o[7] = bf16_hi(r.w);
+    }
+};
+template <> struct Loader<HOSCF_FP8E4M3, 16> {
+    using A = float;
+    using Raw = u32x4;
+    __device__ static Raw zero() { return Raw{0u, 0u, 0u, 0u}; }
+    __device__ static Raw load(const uint8_t* p) { return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)); }
+    __device__ static void cvt(Raw r, A* o) {
+        e4m3x4(r.x, o); e4m3x4(r.y, o + 4); e4m3x4(r.z, o + 8); e4m3x4(r.w, o + 12);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Transposed butterfly: N values per lane are summed over the 2^STEPS lanes
+// that differ in lane bits [LO, LO+STEPS).  The top bits halve the values each
+// step (each lane keeps one half and adds its partner's copy of it); once one
+// value is left the remaining bits are a plain butterfly.  On return value j
+// of the lane is the total of original index base + j.
+// ---------------------------------------------------------------------------
+template <typename A, int N, int STEPS, int LO>
+__device__ __forceinline__ void xred(A* v, int lane, int& base) {
+    if constexpr (STEPS > 0) {
+        constexpr int mask = 1 << (LO + STEPS - 1);
+        if constexpr (N > 1) {
+            constexpr int H = N / 2;
+            const bool up = (lane & mask) != 0;
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                A send = up ? v[j] : v[j + H];
+                A keep = up ? v[j + H] : v[j];
+                v[j] = keep + __shfl_xor(send, mask);
+            }
+            base += up ? H : 0;
+            xred<A, H, STEPS - 1, LO>(v, lane, base);
+        } else {
+            v[0] += __shfl_xor(v[0], mask);
+            xred<A, 1, STEPS - 1, LO>(v, lane, base);
+        }
+    }
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// ---------------------------------------------------------------------------
+// K1: the three-output streaming kernel.
+// ---------------------------------------------------------------------------
+template <int FMT, int VEC, int LR, int MB>
+__global__ __launch_bounds__(256) void ttvc3_kernel(Ttvc3Args args) {
+    using L = Loader<FMT, VEC>;
+    using A = typename Fmt<FMT>::A;
+    using S = typename Fmt<FMT>::S;
+    constexpr int G = 64 / LR;              // rows per wave instruction
+    constexpr int QW = LR * VEC;            // q-chunk width
+    constexpr int WM = G * MB;              // rows of one wave's m-tile
+    constexpr int KS = (32768 / (256 * VEC * (int)sizeof(A))) > 0 ? (32768 / (256 * VEC * (int)sizeof(A))) : 1;
+    __shared__ A cbuf[KS * 4 * G * QW];     // = KS * 256 * VEC values
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane / LR, c = lane % LR;
+    const int64_t P = args.P, M = args.M, Q = args.Q;
+    int64_t bid = blockIdx.x;
+    const int qc = (int)(bid % args.nq);
+    bid /= args.nq;
+    const int64_t mtw = bid % args.nmt;
+    const int64_t pt = bid / args.nmt;
+
+    const int64_t q0 = (int64_t)qc * args.QWe + (int64_t)c * VEC;
+    const bool qok = (c * VEC < args.QWe) && (q0 < Q);
+    const int64_t mrow0 = (mtw * 4 + wave) * WM + g;
+    const int64_t p0 = pt * args.BP;
+    const int64_t p1 = p0 + args.BP < P ? p0 + args.BP : P;
+    const A* xp = static_cast<const A*>(args.xp);
+    const A* xq = static_cast<const A*>(args.xq);
+    const A* w = static_cast<const A*>(args.w);
+    const A scale = A(args.scale);
+
+    A xqv[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) xqv[v] = qok ? xq[q0 + v] : A(0);
+    A wm[MB];
+    bool rok[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int64_t m = mrow0 + (int64_t)G * i;
+        rok[i] = qok && (m < M);
+        wm[i] = (m < M) ? w[m] : A(0);
+    }
+    A accR[MB][VEC];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) accR[i][v] = A(0);
+
+    const S* Tb = static_cast<const S*>(args.T);
+    A* Lout = static_cast<A*>(args.L);
+    A* Rout = static_cast<A*>(args.R);
+    A* Cout = static_cast<A*>(args.C);
+    int slot = 0;
+    for (int64_t p = p0; p < p1; ++p) {
+        const A xpp = xp[p];
+        const S* rowp = Tb + (p * M + mrow0) * Q + q0;
+        typename L::Raw raw[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) raw[i] = rok[i] ? L::load(rowp + (int64_t)i * G * Q) : L::zero();
+        A accC[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) accC[v] = A(0);
+        A dl[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            A e[VEC];
+            L::cvt(raw[i], e);
+            A d = A(0);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                accR[i][v] = fma(e[v], xpp, accR[i][v]);
+                accC[v] = fma(e[v], wm[i], accC[v]);
+                d = fma(e[v], xqv[v], d);
+            }
+            dl[i] = d;
+        }
+        if (args.doL) {
+            int base = 0;
+            xred<A, MB, ilog2(LR), 0>(dl, lane, base);
+            constexpr int HS = ilog2(LR) < ilog2(MB) ? ilog2(LR) : ilog2(MB);
+            constexpr int NR = MB >> HS;
+            constexpr int FULL = ilog2(LR) - HS;
+            if ((c & ((1 << FULL) - 1)) == 0) {
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const int64_t m = mrow0 + (int64_t)G * (base + j);
+                    if (m < M) Lout[((int64_t)qc * P + p) * M + m] = dl[j] * scale;
+                }
+            }
+        }
+        if (args.doC) {
+            A* dst = cbuf + ((slot * 4 + wave) * G + g) * QW + c * VEC;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) dst[v] = accC[v];
+            ++slot;
+            if (slot == KS || p == p1 - 1) {
+                __syncthreads();
+                const int nval = slot * QW;
+                for (int idx = tid; idx < nval; idx += 256) {
+                    const int s = idx / QW, qi = idx - s * QW;
+                    const A* src = cbuf + (s * 4 * G) * QW + qi;
+                    A sum = A(0);
+                    for (int k = 0; k < 4 * G; ++k) sum += src[k * QW];
+                    const int64_t q = (int64_t)qc * args.QWe + qi;
+                    const int64_t pp = p - slot + 1 + s;
+                    if (qi < args.QWe && q < Q) Cout[(mtw * P + pp) * Q + q] = sum * scale;
+                }
+                __syncthreads();
+                slot = 0;
+            }
+        }
+    }
+    if (args.doR) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            if (!rok[i]) continue;
+            const int64_t m = mrow0 + (int64_t)G * i;
+            A* dst = Rout + (pt * M + m) * Q + q0;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) dst[v] = accR[i][v] * scale;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: dst[i] = sum_k src[k*n + i] in a fixed order (FP64 accumulation).
+// ---------------------------------------------------------------------------
+template <typename A>
+__global__ __launch_bounds__(256) void reduce_parts_kernel(ReduceJobs jobs) {
+    const int j = blockIdx.y;
+    const A* src = static_cast<const A*>(jobs.src[j]);
+    A* dst = static_cast<A*>(jobs.dst[j]);
+    const int64_t n = jobs.n[j];
+    const int K = jobs.K[j];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s += (double)src[(int64_t)k * n + i];
+        dst[i] = A(s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Factor preparation: unit blocks (eq. factor) in FP64 and in the sweep's
+// accumulation type; flags a zero or non-finite block.
+// ---------------------------------------------------------------------------
+template <typename A>
+__global__ __launch_bounds__(1024) void prep_factors_kernel(const double* x, int N, FactorOffsets off,
+                                                            double* xu, A* xa, SolveState* st) {
+    __shared__ double red[1024 / 64];
+    __shared__ double nrm_s;
+    const int tid = threadIdx.x;
+    for (int n = 0; n < N; ++n) {
+        const int64_t o = off.off[n], d = off.off[n + 1] - off.off[n];
+        double s = 0.0;
+        for (int64_t i = tid; i < d; i += 1024) s += x[o + i] * x[o + i];
+        for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k);
+        if ((tid & 63) == 0) red[tid >> 6] = s;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int k = 0; k < 1024 / 64; ++k) t += red[k];
+            nrm_s = sqrt(t);
+            if (!(t > 0.0)) st->degenerate = 1;
+            if (!isfinite(t)) st->nonfinite = 1;
+        }
+        __syncthreads();
+        const double nrm = nrm_s;
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int64_t i = tid; i < d; i += 1024) {
+            const double u = x[o + i] * inv;
+            xu[o + i] = u;
+            xa[o + i] = A(u);
+        }
+        __syncthreads();
+    }
+}
+
+// w[m] = prod_k u_{mode k}[i_k] over the middle modes (C order).
+template <typename A>
+__global__ __launch_bounds__(256) void kron_kernel(const double* xu, KronArgs k, A* w) {
+    for (int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x; m < k.M; m += (int64_t)gridDim.x * 256) {
+        int64_t idx = m;
+        double prod = 1.0;
+        for (int j = k.nmid - 1; j >= 0; --j) {
+            const int64_t i = idx % k.dim[j];
+            idx /= k.dim[j];
+            prod *= xu[k.off[j] + i];
+        }
+        w[m] = A(prod);
+    }
+}
+
+// Order-2 tensors: the single block A_{1,2} is T itself (Section 3, matrix
+// case); widen the stored values (times the scale) into the block buffer.
+template <int FMT, typename B>
+__global__ __launch_bounds__(256) void convert_kernel(const void* src, int64_t n, float scale, B* dst) {
+    using S = typename Fmt<FMT>::S;
+    const S* p = static_cast<const S*>(src);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        typename Fmt<FMT>::A v[1];
+        Loader<FMT, 1>::cvt(p[i], v);
+        dst[i] = B(v[0]) * B(scale);
+    }
+}
+
+// Transposed copies of the packed blocks (A_{m,n}' is I_n x I_m at the same
+// offset), one 32 x 32 tile per workgroup through LDS.
+template <typename B>
+__global__ __launch_bounds__(256) void transpose_kernel(const B* __restrict__ blocks, TransposeArgs t,
+                                                         B* __restrict__ out) {
+    __shared__ B tile[32 * 33];
+    int64_t id = blockIdx.x;
+    int b = 0;
+    while (id >= t.tiles_first[b + 1]) ++b;
+    id -= t.tiles_first[b];
+    const int64_t Im = t.rows[b], In = t.cols[b];
+    const int64_t tj = (In + 31) / 32;
+    const int64_t i0 = (id / tj) * 32, j0 = (id % tj) * 32;
+    const B* A = blocks + t.off[b];
+    B* AT = out + t.off[b];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t i = i0 + y, j = j0 + tx;
+        tile[y * 33 + tx] = (i < Im && j < In) ? A[i * In + j] : B(0);
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t j = j0 + y, i = i0 + tx;
+        if (i < Im && j < In) AT[j * Im + i] = tile[tx * 33 + y];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side: launch selection and the order-N recursion plan.
+// ---------------------------------------------------------------------------
+static int pow2_at_least(int64_t v) {
+    int p = 1;
+    while (p < v && p < 64) p <<= 1;
+    return p;
+}
+
+template <int FMT, int VEC, int MB>
+static hipError_t launch_lr(int LR, dim3 grid, const Ttvc3Args& a, hipStream_t s) {
+    switch (LR) {
+        case 1: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 1, MB>), grid, dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 2, MB>), grid, dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 4, MB>), grid, dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 8, MB>), grid, dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 16, MB>), grid, dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 32, MB>), grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 64, MB>), grid, dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+// Rows per lane-group for each storage format (register budget of R).
+template <int FMT> constexpr int mb_vec() { return FMT == HOSCF_F64 ? 16 : FMT == HOSCF_F32 ? 16 : FMT == HOSCF_BF16 ? 8 : 4; }
+
+// Resident workgroups of the three-output kernel per CU (register-limited),
+// and the CU count, for grid sizing.
+static int resident_slots(int fmt, int VEC, int LR) {
+    static int cached[4][2][8] = {};
+    const int li = LR == 1 ? 0 : LR == 2 ? 1 : LR == 4 ? 2 : LR == 8 ? 3 : LR == 16 ? 4 : LR == 32 ? 5 : 6;
+    int& c = cached[fmt][VEC > 1][li];
+    if (c) return c;
+    int dev = 0, cus = 256, per = 2;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void* fn = nullptr;
+#define HOSCF_FN(F, V, MB)                                                                               \
+    switch (LR) {                                                                                        \
+        case 1: fn = (const void*)&ttvc3_kernel<F, V, 1, MB>; break;                                     \
+        case 2: fn = (const void*)&ttvc3_kernel<F, V, 2, MB>; break;                                     \
+        case 4: fn = (const void*)&ttvc3_kernel<F, V, 4, MB>; break;                                     \
+        case 8: fn = (const void*)&ttvc3_kernel<F, V, 8, MB>; break;                                     \
+        case 16: fn = (const void*)&ttvc3_kernel<F, V, 16, MB>; break;                                   \
+        case 32: fn = (const void*)&ttvc3_kernel<F, V, 32, MB>; break;                                   \
+        default: fn = (const void*)&ttvc3_kernel<F, V, 64, MB>; break;                                   \
+    }
+    if (VEC == 1) {
+        switch (fmt) {
+            case HOSCF_F64: fn = (const void*)&ttvc3_kernel<HOSCF_F64, 1, 64, 16>; break;
+            case HOSCF_F32: fn = (const void*)&ttvc3_kernel<HOSCF_F32, 1, 64, 16>; break;
+            case HOSCF_BF16: fn = (const void*)&ttvc3_kernel<HOSCF_BF16, 1, 64, 16>; break;
+            default: fn = (const void*)&ttvc3_kernel<HOSCF_FP8E4M3, 1, 64, 16>; break;
+        }
+    } else {
+        switch (fmt) {
+            case HOSCF_F64: HOSCF_FN(HOSCF_F64, 2, 16); break;
+            case HOSCF_F32: HOSCF_FN(HOSCF_F32, 4, 16); break;
+            case HOSCF_BF16: HOSCF_FN(HOSCF_BF16, 8, 8); break;
+            default: HOSCF_FN(HOSCF_FP8E4M3, 16, 4); break;
+        }
+    }
+#undef HOSCF_FN
+    if (fn) hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0);
+    c = std::max(1, cus * std::max(1, per));
+    return c;
+}
+
+Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, int64_t target_waves, int64_t bp_min) {
+    Ttvc3Shape s;
+    static const int vecs[4] = {2, 4, 8, 16};
+    static const int mbs[4] = {16, 16, 8, 4};
+    static const int esz[4] = {8, 4, 2, 1};
+    s.VEC = (Q % vecs[fmt] == 0) ? vecs[fmt] : 1;
+    s.MB = s.VEC > 1 ? mbs[fmt] : 16;
+    s.LR = s.VEC > 1 ? pow2_at_least((Q + s.VEC - 1) / s.VEC) : 64;
+    if (s.LR < 1) s.LR = 1;
+    const int G = 64 / s.LR;
+    s.QW = s.LR * s.VEC;
+    s.nq = (int)((Q + s.QW - 1) / s.QW);
+    // equal q-chunks: ceil(Q / nq) rounded up to whole vectors
+    const int64_t per_chunk = (Q + s.nq - 1) / s.nq;
+    s.QWe = (int)(((per_chunk + s.VEC - 1) / s.VEC) * s.VEC);
+    const int64_t wm = (int64_t)G * s.MB;
+    const int64_t nmt_w = (M + wm - 1) / wm;
+    s.nmt = (nmt_w + 3) / 4;
+    const int64_t cols = (int64_t)s.nq * s.nmt;
+    // p-split: balance rounds of resident workgroups against the R partials it
+    // creates (npt copies of M x Q accumulators, written and read back).
+    const int64_t slots = target_waves > 0 ? std::max<int64_t>(1, target_waves / 4) : resident_slots(fmt, s.VEC, s.LR);
+    const double tbytes = (double)P * (double)M * (double)Q * esz[fmt];
+    const double accb = fmt == HOSCF_F64 ? 8.0 : 4.0;
+    double best = 1e300;
+    int64_t best_np = 1;
+    const int64_t np_max = std::max<int64_t>(1, std::min<int64_t>(P, (P + bp_min - 1) / std::max<int64_t>(1, bp_min)));
+    for (int64_t np = 1; np <= np_max; ++np) {
+        const int64_t bp = (P + np - 1) / np;
+        const int64_t npt = (P + bp - 1) / bp;
+        const int64_t W = cols * npt;
+        const double rounds = std::ceil((double)W / (double)slots);
+        const double stream = rounds * (double)slots / (double)W;  // >= 1: idle share of the last round
+        const double partial = 2.0 * (double)(npt > 1 ? npt : 0) * (double)M * (double)Q * accb / tbytes;
+        const double under = W < slots ? (double)slots / (double)W : 1.0;  // too few workgroups to fill the chip
+        const double cost = std::max(stream, under) + partial;
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_np = npt;
+        }
+    }
+    s.BP = (P + best_np - 1) / best_np;
+    s.npt = (P + s.BP - 1) / s.BP;
+    return s;
+}
+
+template <int FMT>
+static hipError_t launch_ttvc3_fmt(const Ttvc3Shape& sh, const Ttvc3Args& a, hipStream_t s) {
+    const dim3 grid((unsigned)((int64_t)sh.nq * sh.nmt * sh.npt));
+    constexpr int V = Fmt<FMT>::VEC;
+    constexpr int MBV = mb_vec<FMT>();
+    if (sh.VEC == V) return launch_lr<FMT, V, MBV>(sh.LR, grid, a, s);
+    hipLaunchKernelGGL((ttvc3_kernel<FMT, 1, 64, 16>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ttvc3(int fmt, const Ttvc3Shape& sh, const Ttvc3Args& a, hipStream_t s) {
+    switch (fmt) {
+        case HOSCF_F64: return launch_ttvc3_fmt<HOSCF_F64>(sh, a, s);
+        case HOSCF_F32: return launch_ttvc3_fmt<HOSCF_F32>(sh, a, s);
+        case HOSCF_BF16: return launch_ttvc3_fmt<HOSCF_BF16>(sh, a, s);
+        case HOSCF_FP8E4M3: return launch_ttvc3_fmt<HOSCF_FP8E4M3>(sh, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(bool f64, const ReduceJobs& jobs, int njobs, hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    int64_t nmax = 0;
+    for (int j = 0; j < njobs; ++j) nmax = std::max(nmax, jobs.n[j]);
+    int64_t blocks = std::min<int64_t>((nmax + 255) / 256, 4096);
+    dim3 grid((unsigned)std::max<int64_t>(blocks, 1), njobs);
+    if (f64) hipLaunchKernelGGL(reduce_parts_kernel<double>, grid, dim3(256), 0, s, jobs);
+    else hipLaunchKernelGGL(reduce_parts_kernel<float>, grid, dim3(256), 0, s, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(bool f64, const double* x, int N, const FactorOffsets& off, double* xu, void* xa,
+                       SolveState* st, hipStream_t s) {
+    if (f64) hipLaunchKernelGGL(prep_factors_kernel<double>, dim3(1), dim3(1024), 0, s, x, N, off, xu, (double*)xa, st);
+    else hipLaunchKernelGGL(prep_factors_kernel<float>, dim3(1), dim3(1024), 0, s, x, N, off, xu, (float*)xa, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_kron(bool f64, const double* xu, const KronArgs& k, void* w, hipStream_t s) {
+    int64_t blocks = std::min<int64_t>((k.M + 255) / 256, 2048);
+    if (f64) hipLaunchKernelGGL(kron_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, xu, k, (double*)w);
+    else hipLaunchKernelGGL(kron_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, xu, k, (float*)w);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(bool f64, const void* blocks, const TransposeArgs& t, void* out, hipStream_t s) {
+    const dim3 grid((unsigned)t.tiles_first[t.nblk]);
+    if (f64) hipLaunchKernelGGL(transpose_kernel<double>, grid, dim3(256), 0, s, (const double*)blocks, t, (double*)out);
+    else hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(256), 0, s, (const float*)blocks, t, (float*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int fmt, const void* src, int64_t n, float scale, bool f64, void* dst, hipStream_t s) {
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)));
+    if (f64) {
+        hipLaunchKernelGGL((convert_kernel<HOSCF_F64, double>), grid, dim3(256), 0, s, src, n, scale, (double*)dst);
+        return hipGetLastError();
+    }
+    switch (fmt) {
+        case HOSCF_F32: hipLaunchKernelGGL((convert_kernel<HOSCF_F32, float>), grid, dim3(256), 0, s, src, n, scale, (float*)dst); break;
+        case HOSCF_BF16: hipLaunchKernelGGL((convert_kernel<HOSCF_BF16, float>), grid, dim3(256), 0, s, src, n, scale, (float*)dst); break;
+        case HOSCF_FP8E4M3: hipLaunchKernelGGL((convert_kernel<HOSCF_FP8E4M3, float>), grid, dim3(256), 0, s, src, n, scale, (float*)dst); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hoscf

@@ -1,0 +1,260 @@
+"""Python binding of libhoscf (ctypes).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory, the current stream and the autograd wrapper.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhoscf.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_01778_amd.build_lib` "
+                      "(or __graft_entry__.build()); there is no fallback path")
+_lib = ctypes.CDLL(LIB_PATH)
+
+MAX_ORDER = 8
+F64, F32, BF16, FP8E4M3 = 0, 1, 2, 3
+OP_TTVC, OP_SOLVE, OP_BACKWARD, OP_TTVC_BACKWARD, OP_QUANTIZE = 0, 1, 2, 3, 4
+OK, NOT_CONVERGED, INVALID_ARG, HIP_ERROR, NONFINITE, DEGENERATE, WORKSPACE_TOO_SMALL = 0, 1, -1, -2, -3, -4, -5
+
+
+class HoscfTensor(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("dims", ctypes.c_int64 * MAX_ORDER), ("dtype", ctypes.c_int32),
+                ("data", ctypes.c_void_p), ("scale", ctypes.c_float), ("data_f32", ctypes.c_void_p)]
+
+
+class HoscfOptions(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("tol_lp", ctypes.c_double), ("max_refine", ctypes.c_int32), ("canonical_sign", ctypes.c_int32),
+                ("stall_iters", ctypes.c_int32)]
+
+
+class HoscfInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("rqi_accepted", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("lp_sweeps", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("lambda_", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_lib.hoscf_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(HoscfTensor), ctypes.POINTER(HoscfOptions)]
+_lib.hoscf_workspace_size.restype = ctypes.c_size_t
+_lib.hoscf_status_string.argtypes = [ctypes.c_int]
+_lib.hoscf_status_string.restype = ctypes.c_char_p
+_lib.hoscf_ttvc.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.hoscf_ttvc.restype = ctypes.c_int
+_lib.hoscf_solve.argtypes = [ctypes.POINTER(HoscfTensor), _P, ctypes.POINTER(HoscfOptions), _P,
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(HoscfInfo), _P, ctypes.c_size_t, _P]
+_lib.hoscf_solve.restype = ctypes.c_int
+_lib.hoscf_quantize.argtypes = [_P, ctypes.c_int64, ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.hoscf_quantize.restype = ctypes.c_int
+_lib.hoscf_backward.argtypes = [ctypes.POINTER(HoscfTensor), _P, ctypes.c_double, ctypes.c_double, _P, _P,
+                                ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.hoscf_backward.restype = ctypes.c_int
+_lib.hoscf_ttvc_backward.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, _P, ctypes.c_double, _P,
+                                     ctypes.c_int, _P, _P, ctypes.c_size_t, _P]
+_lib.hoscf_ttvc_backward.restype = ctypes.c_int
+_lib.hoscf_profile_sweep.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _P,
+                                     ctypes.c_size_t, _P]
+_lib.hoscf_profile_sweep.restype = ctypes.c_int
+_lib.hoscf_batch_plan_create.argtypes = [ctypes.c_int, ctypes.POINTER(HoscfTensor), ctypes.c_int,
+                                         ctypes.POINTER(HoscfOptions), ctypes.POINTER(ctypes.c_void_p)]
+_lib.hoscf_batch_plan_create.restype = ctypes.c_int
+_lib.hoscf_plan_destroy.argtypes = [_P]
+_lib.hoscf_plan_destroy.restype = None
+_lib.hoscf_batch_workspace_size.argtypes = [_P]
+_lib.hoscf_batch_workspace_size.restype = ctypes.c_size_t
+_lib.hoscf_solve_batched.argtypes = [_P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.hoscf_solve_batched.restype = ctypes.c_int
+
+
+class HoscfError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+def status_string(code: int) -> str:
+    return _lib.hoscf_status_string(int(code)).decode()
+
+
+def _check(code: int, what: str, allow_not_converged: bool = False) -> int:
+    if code == OK or (allow_not_converged and code == NOT_CONVERGED):
+        return code
+    raise HoscfError(code, what)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+_DT = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float8_e4m3fn: FP8E4M3,
+       torch.uint8: FP8E4M3}
+
+
+def describe(T: torch.Tensor, scale: float = 1.0, data_f32: Optional[torch.Tensor] = None) -> HoscfTensor:
+    """C descriptor of a dense contiguous device tensor."""
+    if T.dim() < 2 or T.dim() > MAX_ORDER:
+        raise ValueError("order must be in [2, 8]")
+    if T.dtype not in _DT:
+        raise TypeError(f"unsupported dtype {T.dtype}")
+    if not T.is_contiguous():
+        raise ValueError("tensor must be contiguous (C order)")
+    d = HoscfTensor()
+    d.order = T.dim()
+    for i, s in enumerate(T.shape):
+        d.dims[i] = int(s)
+    d.dtype = _DT[T.dtype]
+    d.data = T.data_ptr()
+    d.scale = float(scale)
+    d.data_f32 = None if data_f32 is None else data_f32.data_ptr()
+    return d
+
+
+def workspace_size(op: int, desc: HoscfTensor, opts: Optional[HoscfOptions] = None) -> int:
+    return int(_lib.hoscf_workspace_size(op, ctypes.byref(desc), ctypes.byref(opts) if opts is not None else None))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def block_shapes(dims: Sequence[int]) -> List[Tuple[int, int]]:
+    N = len(dims)
+    return [(dims[m], dims[n]) for m in range(N) for n in range(m + 1, N)]
+
+
+def unpack_blocks(flat: torch.Tensor, dims: Sequence[int]) -> List[torch.Tensor]:
+    out, off = [], 0
+    for (a, b) in block_shapes(dims):
+        out.append(flat[off:off + a * b].view(a, b))
+        off += a * b
+    return out
+
+
+@dataclass
+class TtvcResult:
+    blocks: List[torch.Tensor]   # raw A_{m,n}, packed order (1,2),(1,3),...,(N-1,N)
+    blocks_flat: torch.Tensor
+    g: torch.Tensor              # [D] FP64 mode vectors
+    sigma: float
+    residual: float
+    normJ: float
+    scalars: torch.Tensor
+
+
+def ttvc(T: torch.Tensor, x: torch.Tensor, scale: float = 1.0) -> TtvcResult:
+    """One TTVc sweep (all J blocks, mode vectors, sigma, residual) at x."""
+    desc = describe(T, scale)
+    dims = list(T.shape)
+    bdt = torch.float64 if T.dtype == torch.float64 else torch.float32
+    nb = sum(a * b for a, b in block_shapes(dims))
+    blocks = torch.empty(nb, dtype=bdt, device=T.device)
+    g = torch.empty(sum(dims), dtype=torch.float64, device=T.device)
+    sc = torch.empty(4, dtype=torch.float64, device=T.device)
+    x = x.to(device=T.device, dtype=torch.float64).contiguous()
+    ws = _workspace(workspace_size(OP_TTVC, desc), T.device)
+    _check(_lib.hoscf_ttvc(ctypes.byref(desc), x.data_ptr(), blocks.data_ptr(), g.data_ptr(), sc.data_ptr(),
+                           ws.data_ptr(), ws.numel(), _stream()), "hoscf_ttvc")
+    s = sc.cpu()
+    return TtvcResult(unpack_blocks(blocks, dims), blocks, g, float(s[0]), float(s[1]), float(s[2]), sc)
+
+
+def profile_sweep(T: torch.Tensor, x: torch.Tensor, reps: int = 10, scale: float = 1.0):
+    """HIP-event timings (ms per sweep) of a sweep: (whole sweep, all TTVc
+    kernel launches, level-1 TTVc launch) and the algorithmic bytes of T."""
+    desc = describe(T, scale)
+    dims = list(T.shape)
+    bdt = torch.float64 if T.dtype == torch.float64 else torch.float32
+    nb = sum(a * b for a, b in block_shapes(dims))
+    blocks = torch.empty(nb, dtype=bdt, device=T.device)
+    g = torch.empty(sum(dims), dtype=torch.float64, device=T.device)
+    x = x.to(device=T.device, dtype=torch.float64).contiguous()
+    ws = _workspace(workspace_size(OP_TTVC, desc), T.device)
+    out = (ctypes.c_double * 3)()
+    nbytes = ctypes.c_int64(0)
+    _check(_lib.hoscf_profile_sweep(ctypes.byref(desc), x.data_ptr(), blocks.data_ptr(), g.data_ptr(), int(reps), out,
+                                    ctypes.byref(nbytes), ws.data_ptr(), ws.numel(), _stream()), "hoscf_profile_sweep")
+    return float(out[0]), float(out[1]), float(out[2]), int(nbytes.value)
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    sweeps: int
+    rqi_accepted: int
+    lp_sweeps: int
+    lanczos_steps: int
+    residual: float
+    sigma: float
+
+    @property
+    def status_name(self) -> str:
+        return status_string(self.status)
+
+
+def options(algo: str = "hoscf", tol: float = 1e-10, max_iter: int = 500, tol_lp: float = 1e-3,
+            max_refine: int = 0, canonical_sign: bool = True, stall_iters: int = 0) -> HoscfOptions:
+    o = HoscfOptions()
+    o.algo = {"hoscf": 0, "ihoscf": 1}[algo]
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.tol_lp = float(tol_lp)
+    o.max_refine = int(max_refine)
+    o.canonical_sign = 1 if canonical_sign else 0
+    o.stall_iters = int(stall_iters)
+    return o
+
+
+def solve_raw(T: torch.Tensor, x0: torch.Tensor, opts: HoscfOptions, scale: float = 1.0,
+              data_f32: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+              raise_on_error: bool = True) -> Tuple[float, torch.Tensor, SolveInfo]:
+    desc = describe(T, scale, data_f32)
+    x0 = x0.to(device=T.device, dtype=torch.float64).contiguous()
+    x = torch.empty_like(x0)
+    need = workspace_size(OP_SOLVE, desc, opts)
+    ws = workspace if (workspace is not None and workspace.numel() >= need) else _workspace(need, T.device)
+    sig = ctypes.c_double(0.0)
+    info = HoscfInfo()
+    code = _lib.hoscf_solve(ctypes.byref(desc), x0.data_ptr(), ctypes.byref(opts), x.data_ptr(), ctypes.byref(sig),
+                            ctypes.byref(info), ws.data_ptr(), ws.numel(), _stream())
+    if raise_on_error:
+        _check(code, "hoscf_solve", allow_not_converged=True)
+    si = SolveInfo(code, info.iters, info.sweeps, info.rqi_accepted, info.lp_sweeps, info.lanczos_steps,
+                   info.residual, info.lambda_)
+    return float(sig.value), x, si
+
+
+def quantize(T32: torch.Tensor, fmt: str) -> Tuple[torch.Tensor, torch.Tensor]:
+    """FP32 -> ('bf16' | 'fp8') copy and its scale (a 1-element FP32 device tensor)."""
+    if T32.dtype != torch.float32 or not T32.is_contiguous():
+        raise ValueError("quantize takes a contiguous float32 tensor")
+    dt = {"bf16": (BF16, torch.bfloat16), "fp8": (FP8E4M3, torch.float8_e4m3fn)}[fmt]
+    out = torch.empty(T32.shape, dtype=dt[1], device=T32.device)
+    scale = torch.empty(1, dtype=torch.float32, device=T32.device)
+    ws = _workspace(256, T32.device)
+    _check(_lib.hoscf_quantize(T32.data_ptr(), T32.numel(), dt[0], out.data_ptr(), scale.data_ptr(), ws.data_ptr(),
+                               ws.numel(), _stream()), "hoscf_quantize")
+    return out, scale
+
+
+def split(x: torch.Tensor, dims: Sequence[int]) -> List[torch.Tensor]:
+    out, off = [], 0
+    for d in dims:
+        out.append(x[off:off + d])
+        off += d
+    return out

@@ -1,0 +1,87 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/hoscf.h declares, sizes workspaces and rejects bad arguments before
+launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hoscf.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(hoscf_[a-z0-9_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["hoscf_ttvc", "hoscf_solve", "hoscf_solve_batched", "hoscf_backward",
+                     "hoscf_workspace_size", "hoscf_status_string", "hoscf_quantize"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = ctypes.CDLL(lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(so, name), name
+
+
+def test_status_strings(lib):
+    assert lib.status_string(0) == "OK"
+    assert lib.status_string(-5) == "WORKSPACE_TOO_SMALL"
+    assert lib.status_string(1) == "NOT_CONVERGED"
+
+
+def _desc(lib, dims, dtype=1, data=0x1000, scale=1.0):
+    d = lib.HoscfTensor()
+    d.order = len(dims)
+    for i, s in enumerate(dims[:8]):
+        d.dims[i] = s
+    d.dtype = dtype
+    d.data = data
+    d.scale = scale
+    d.data_f32 = None
+    return d
+
+
+def test_workspace_sizes(lib):
+    small = lib.workspace_size(lib.OP_TTVC, _desc(lib, [8, 9, 10]))
+    big = lib.workspace_size(lib.OP_TTVC, _desc(lib, [800, 800, 800]))
+    assert 0 < small < big
+    assert lib.workspace_size(lib.OP_SOLVE, _desc(lib, [8, 9, 10])) > small
+    # order 4: recursion intermediates are counted
+    assert lib.workspace_size(lib.OP_TTVC, _desc(lib, [50, 50, 50, 50])) > 2 * 50 ** 3 * 4
+    # invalid descriptors size to 0
+    assert lib.workspace_size(lib.OP_TTVC, _desc(lib, [8])) == 0
+    assert lib.workspace_size(lib.OP_TTVC, _desc(lib, [8, 0, 3])) == 0
+    assert lib.workspace_size(lib.OP_TTVC, _desc(lib, [2] * 9)) == 0
+    assert lib.workspace_size(lib.OP_TTVC, _desc(lib, [4, 4, 4], dtype=3, scale=0.0)) == 0
+
+
+def test_invalid_arguments_rejected_without_launch(lib):
+    so = lib._lib
+    good = _desc(lib, [4, 5, 6])
+    # null data
+    bad = _desc(lib, [4, 5, 6], data=0)
+    assert so.hoscf_ttvc(ctypes.byref(bad), 0x10, 0x10, 0x10, 0x10, 0x10, 1 << 20, None) == lib.INVALID_ARG
+    # order 1 and 9
+    assert so.hoscf_ttvc(ctypes.byref(_desc(lib, [7])), 0x10, 0x10, 0x10, 0x10, 0x10, 1 << 20, None) == lib.INVALID_ARG
+    # null factor / outputs
+    assert so.hoscf_ttvc(ctypes.byref(good), None, 0x10, 0x10, 0x10, 0x10, 1 << 20, None) == lib.INVALID_ARG
+    # unknown dtype
+    assert so.hoscf_ttvc(ctypes.byref(_desc(lib, [4, 5, 6], dtype=7)), 0x10, 0x10, 0x10, 0x10, 0x10, 1 << 20,
+                         None) == lib.INVALID_ARG
+    # workspace too small (checked before any launch)
+    assert so.hoscf_ttvc(ctypes.byref(good), 0x10, 0x10, 0x10, 0x10, 0x10, 16, None) == lib.WORKSPACE_TOO_SMALL
+    opts = lib.options(algo="hoscf")
+    opts.algo = 5
+    sig = ctypes.c_double()
+    info = lib.HoscfInfo()
+    assert so.hoscf_solve(ctypes.byref(good), 0x10, ctypes.byref(opts), 0x10, ctypes.byref(sig), ctypes.byref(info),
+                          0x10, 1 << 30, None) == lib.INVALID_ARG
+    assert so.hoscf_quantize(0x10, 10, 1, 0x10, 0x10, 0x10, 256, None) == lib.INVALID_ARG
