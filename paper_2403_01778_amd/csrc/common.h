@@ -57,11 +57,12 @@ struct SolveState {
     int32_t pad;
     unsigned bar[2];     // grid barrier: arrival count, generation
     // phase timestamps of the last post-sweep launch per kind (epilogue-only
-    // at [0..9], eigen / Rayleigh at [10..19]; constant 100 MHz clock):
+    // at [0..15], eigen / Rayleigh at [16..31]; constant 100 MHz clock):
     // +0 start, +1 J x done, +2 sigma reduced, +3 residual reduced,
     // +4 Lanczos step 0 done, +5 step 1 J v done, +6 step 1 done,
-    // +7 Lanczos done, +8 end; +9 Lanczos steps
-    uint64_t trace[20];
+    // +7 Lanczos done, +8 end, +9 Lanczos steps; within step 1:
+    // +10 first reduction, +11 first update, +12 second reduction, +13 check
+    uint64_t trace[32];
 };
 
 // Packed J-block bookkeeping for an order-N problem.

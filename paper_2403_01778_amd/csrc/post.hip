@@ -23,7 +23,7 @@
 
 namespace hoscf {
 
-constexpr int BS = 256;  // threads per workgroup
+constexpr int BS = 512;  // threads per workgroup
 constexpr int RW = 8;    // J rows a wave reduces together
 
 // ---------------------------------------------------------------------------
@@ -35,12 +35,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum over the workgroup (256 threads); every thread receives the total.
-__device__ double wg_sum(double v, double* lds4) {
+__device__ double wg_sum(double v, double* lds_w) {
     v = wave_sum(v);
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0) lds_w[threadIdx.x >> 6] = v;
     __syncthreads();
-    const double t = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+    double t = 0.0;
+    for (int k = 0; k < BS / 64; ++k) t += lds_w[k];
     __syncthreads();
     return t;
 }
@@ -191,6 +192,18 @@ __device__ bool tri_solve(const double* al, const double* be, int m, double shif
     return true;
 }
 
+// Data one workgroup writes and others read inside the launch (Krylov vectors,
+// reduction partials) moves through device-coherent (agent-scope) atomic
+// loads and stores; everything else uses ordinary cached accesses.  Barriers
+// therefore need no cache-invalidating acquire, and the read-only J blocks
+// stay resident in each XCD's L2 across Lanczos steps.
+__device__ __forceinline__ double ld_ag(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_ag(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // Grid-wide barrier for a co-resident grid (cooperative launch).  Arrival is a
 // device-scope atomic add; the last arrival advances the generation word.
@@ -218,8 +231,9 @@ __device__ void grid_barrier(unsigned* bar, unsigned nwg, int* timeout) {
                 }
             }
         }
-        // acquire once after the wait: later loads see every arrival's stores
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // shared data is read with device-coherent loads after this point, so
+        // only the workgroup's own ordering is needed here
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     __syncthreads();
 }
@@ -233,14 +247,17 @@ struct Lds {
     double red4[BS / 64];
     double part[BS];
     int64_t xoff[kMaxOrder + 1];
+    double fl[kMaxOrder], inv[kMaxOrder];
     double theta, ritz;
     int stop, ok, timeout;
 };
 
 // All-reduce of K per-workgroup partials held in L.mine (alternating
 // buffers, so a fast workgroup never overwrites partials another is still
-// summing).  Totals land in L.hsum.
-__device__ void allreduce(const PostArgs& a, int K, int& parity, Lds& L) {
+// reading).  After the barrier every thread gathers partials with eight loads
+// in flight into LDS (`stage`, kVecLds doubles), then thread k sums column k
+// over the workgroups in workgroup order.  Totals land in L.hsum.
+__device__ void allreduce(const PostArgs& a, int K, int& parity, Lds& L, double* stage) {
     if (a.nwg == 1) {
         __syncthreads();
         for (int k = threadIdx.x; k < K; k += BS) L.hsum[k] = L.mine[k];
@@ -250,27 +267,35 @@ __device__ void allreduce(const PostArgs& a, int K, int& parity, Lds& L) {
     double* buf = a.red + (size_t)parity * a.nwg * a.RK;
     parity ^= 1;
     __syncthreads();
-    for (int k = threadIdx.x; k < K; k += BS) buf[(size_t)blockIdx.x * a.RK + k] = L.mine[k];
+    for (int k = threadIdx.x; k < K; k += BS) st_ag(buf + (size_t)blockIdx.x * a.RK + k, L.mine[k]);
     grid_barrier(a.bar, a.nwg, &L.timeout);
-    for (int k = threadIdx.x; k < K; k += BS) {
-        // eight independent chains (fixed assignment w mod 8), combined pairwise
-        double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int w = 0;
-        for (; w + 8 <= a.nwg; w += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s8[u] += buf[(size_t)(w + u) * a.RK + k];
-        }
-        if (w < a.nwg) {
+    const int kc = std::max(1, std::min(K, kVecLds / a.nwg));  // columns per LDS pass
+    for (int k0 = 0; k0 < K; k0 += kc) {
+        const int kn = std::min(kc, K - k0);
+        const int total = a.nwg * kn;
+        for (int b = threadIdx.x; b < total; b += 8 * BS) {
+            double t[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int wu = w + u < a.nwg ? w + u : 0;
-                const double t = buf[(size_t)wu * a.RK + k];
-                s8[u] += (w + u < a.nwg) ? t : 0.0;
+                const int idx = b + u * BS;
+                const int ic = idx < total ? idx : 0;
+                const int w = ic / kn, k = ic - w * kn;
+                t[u] = ld_ag(buf + (size_t)w * a.RK + k0 + k);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = b + u * BS;
+                if (idx < total) stage[idx] = t[u];
             }
         }
-        L.hsum[k] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+        __syncthreads();
+        for (int k = threadIdx.x; k < kn; k += BS) {
+            double sum = 0.0;
+            for (int w = 0; w < a.nwg; ++w) sum += stage[w * kn + k];
+            L.hsum[k0 + k] = sum;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // Per-thread partial dot products of own rows, summed over the workgroup
@@ -282,13 +307,14 @@ __device__ void wg_to_mine(double v, int k, Lds& L) {
 
 // Copy n doubles from global memory into LDS with eight loads per thread in
 // flight (indices clamped, stores masked).
+template <bool COHERENT>
 __device__ void stage_to_lds(double* dst, const double* src, int64_t n) {
     for (int64_t b = threadIdx.x; b < n; b += 8 * BS) {
         double t[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int64_t i = b + (int64_t)u * BS;
-            t[u] = src[i < n ? i : 0];
+            t[u] = COHERENT ? ld_ag(src + (i < n ? i : 0)) : src[i < n ? i : 0];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -302,77 +328,102 @@ __device__ void stage_to_lds(double* dst, const double* src, int64_t n) {
 // thread's share of the sum over own rows of ||row||^2 when want_fro.  v is
 // staged in LDS when it fits; each lane keeps RW rows x 4 loads in flight.
 template <typename B>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef float T __attribute__((ext_vector_type(4)));
+    static constexpr int E = 4;
+    __device__ static void widen(T v, double* o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+};
+template <>
+struct Vec16<double> {
+    typedef double T __attribute__((ext_vector_type(2)));
+    static constexpr int E = 2;
+    __device__ static void widen(T v, double* o) { o[0] = v.x; o[1] = v.y; }
+};
+
+// Raw (N-1) J v for the workgroup's own rows, written to out[r]; returns the
+// thread's share of the sum over own rows of ||row||^2 when want_fro.  v is
+// staged in LDS when it fits.  A wave takes one row at a time; each segment of
+// the row (a row of a stored block or of its transpose) is read with 16-byte
+// loads, four per lane in flight, when its length and address allow, else
+// element by element.
+template <typename B, bool COHERENT>
 __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, double scale, bool want_fro,
                               int64_t r_lo, int64_t r_hi, double* vlds) {
+    using VT = typename Vec16<B>::T;
+    constexpr int E = Vec16<B>::E;
+    constexpr int U = 4;
     const B* blocks = static_cast<const B*>(a.blocks);
     const B* bt = static_cast<const B*>(a.blocksT);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar table reads
     const bool staged = a.D <= kVecLds;
     if (staged) {
-        stage_to_lds(vlds, v, a.D);
+        stage_to_lds<COHERENT>(vlds, v, a.D);
         __syncthreads();
     }
     const double* vv = staged ? vlds : v;
     double fro = 0.0;
-    for (int64_t r0 = r_lo + (int64_t)wave * RW; r0 < r_hi; r0 += (int64_t)(BS / 64) * RW) {
-        double acc[RW];
-        int nk[RW];
-        int64_t ik[RW];
+    for (int64_t r = r_lo + wave; r < r_hi; r += BS / 64) {
+        int n = 0;
+        while (r >= a.xoff[n + 1]) ++n;
+        const int64_t i = r - a.xoff[n];
+        double acc = 0.0;
+        for (int m = 0; m < a.N; ++m) {
+            if (m == n) continue;
+            const int len = (int)a.dims[m];
+            const B* rowp = (a.seg_src[n][m] ? bt : blocks) + a.seg_base[n][m] + i * (int64_t)len;
+            const double* vm = vv + a.xoff[m];
+            const bool vec = (len % E == 0) && ((reinterpret_cast<uintptr_t>(rowp) & 15) == 0);
+            if (vec) {
+                const VT* rv = reinterpret_cast<const VT*>(rowp);
+                const int nv = len / E;
+                for (int q0 = lane; q0 < nv; q0 += 64 * U) {
+                    VT t[U];
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
-            acc[k] = 0.0;
-            const int64_t r = r0 + k < r_hi ? r0 + k : r_hi - 1;  // clamped: always a valid row
-            int n = 0;
-            while (r >= a.xoff[n + 1]) ++n;
-            nk[k] = n;
-            ik[k] = r - a.xoff[n];
-        }
-        for (int sidx = 0; sidx < a.N - 1; ++sidx) {
-            const B* rowp[RW];
-            const double* vm[RW];
-            int64_t len[RW];
-            int64_t lmax = 0;
-#pragma unroll
-            for (int k = 0; k < RW; ++k) {
-                const int n = nk[k];
-                const int m = sidx < n ? sidx : sidx + 1;  // the sidx-th mode other than n
-                len[k] = (r0 + k < r_hi) ? a.dims[m] : 0;
-                rowp[k] = (a.seg_src[n][m] ? bt : blocks) + a.seg_base[n][m] + ik[k] * a.dims[m];
-                vm[k] = vv + a.xoff[m];
-                lmax = len[k] > lmax ? len[k] : lmax;
-            }
-            for (int64_t j0 = lane; j0 < lmax; j0 += 256) {
-                // every load is issued unconditionally at a clamped, valid index
-                // (index 0 of the same row) and masked afterwards, so all
-                // RW x 4 loads of a lane are in flight together
-                double val[RW][4];
-#pragma unroll
-                for (int k = 0; k < RW; ++k)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t j = j0 + 64 * u;
-                        const int64_t jc = j < len[k] ? j : 0;
-                        const double raw = (double)rowp[k][jc];
-                        val[k][u] = j < len[k] ? raw : 0.0;
+                    for (int u = 0; u < U; ++u) {
+                        const int q = q0 + 64 * u;
+                        t[u] = rv[q < nv ? q : 0];
                     }
 #pragma unroll
-                for (int k = 0; k < RW; ++k)
+                    for (int u = 0; u < U; ++u) {
+                        const int q = q0 + 64 * u;
+                        if (q < nv) {
+                            double e[E];
+                            Vec16<B>::widen(t[u], e);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t j = j0 + 64 * u;
-                        const int64_t jc = j < len[k] ? j : 0;
-                        acc[k] = fma(val[k][u], vm[k][jc], acc[k]);
-                        if (want_fro) fro = fma(val[k][u], val[k][u], fro);
+                            for (int c = 0; c < E; ++c) {
+                                const double vj = (COHERENT && !staged) ? ld_ag(vm + q * E + c) : vm[q * E + c];
+                                acc = fma(e[c], vj, acc);
+                                if (want_fro) fro = fma(e[c], e[c], fro);
+                            }
+                        }
                     }
+                }
+            } else {
+                for (int j0 = lane; j0 < len; j0 += 64 * U) {
+                    B t[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int j = j0 + 64 * u;
+                        t[u] = rowp[j < len ? j : 0];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int j = j0 + 64 * u;
+                        if (j < len) {
+                            const double e = (double)t[u];
+                            const double vj = (COHERENT && !staged) ? ld_ag(vm + j) : vm[j];
+                            acc = fma(e, vj, acc);
+                            if (want_fro) fro = fma(e, e, fro);
+                        }
+                    }
+                }
             }
         }
-        int base = 0;
-        xred64<RW, 6>(acc, lane, base);
-        if ((lane & 7) == 0) {
-            const int64_t r = r0 + base;
-            if (r < r_hi) out[r] = acc[0] * scale;
-        }
+        acc = wave_sum(acc);
+        if (lane == 0) out[r] = acc * scale;
     }
     return fro;
 }
@@ -395,7 +446,7 @@ __device__ void own_dots(const double* V, const double* w, int64_t D, int j, int
             for (int u = 0; u < 8; ++u) {
                 const int i = i0 + u * NW;
                 const int ic = i <= j ? i : 0;
-                const double vi = V[(size_t)ic * D + r];
+                const double vi = ld_ag(V + (size_t)ic * D + r);
                 h[u] = fma(i <= j ? vi : 0.0, wr, h[u]);
             }
         }
@@ -427,7 +478,7 @@ __device__ void own_combine(const double* V, int64_t D, int m, int64_t r_lo, int
             for (int u = 0; u < 8; ++u) {
                 const int i = i0 + u;
                 const int ic = i < m ? i : 0;
-                const double vi = V[(size_t)ic * D + rc];
+                const double vi = ld_ag(V + (size_t)ic * D + rc);
                 acc[u] = fma(i < m ? c[ic] : 0.0, vi, acc[u]);
             }
         }
@@ -456,20 +507,20 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     if (tid <= a.N) L.xoff[tid] = a.xoff[tid];
     __syncthreads();
     const bool tr = blockIdx.x == 0 && tid == 0;
-    uint64_t* trace = a.st->trace + (a.mode == kPostEpilogue ? 0 : 10);
+    uint64_t* trace = a.st->trace + (a.mode == kPostEpilogue ? 0 : 16);
 #define HOSCF_MARK(k) \
     if (tr) trace[k] = __builtin_amdgcn_s_memrealtime()
     HOSCF_MARK(0);
 
     // ---- A. g, sigma, ||J||_F, residual -------------------------------------
-    double fro = matvec_rows<B>(a, a.x, a.g, inv_n1, true, r_lo, r_hi, vlds);
+    double fro = matvec_rows<B, false>(a, a.x, a.g, inv_n1, true, r_lo, r_hi, vlds);
     __syncthreads();
     HOSCF_MARK(1);
     double s0 = 0.0;  // u_1' g_1 over own rows of block 1
     for (int64_t r = r_lo + tid; r < r_hi && r < L.xoff[1]; r += BS) s0 = fma(a.x[r], a.g[r], s0);
     wg_to_mine(s0, 0, L);
     wg_to_mine(fro, 1, L);
-    allreduce(a, 2, parity, L);
+    allreduce(a, 2, parity, L, vlds);
     HOSCF_MARK(2);
     const double sigma = L.hsum[0];
     const double normJ = sqrt(L.hsum[1]) * inv_n1;
@@ -479,7 +530,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         rr = fma(e, e, rr);
     }
     wg_to_mine(rr, 0, L);
-    allreduce(a, 1, parity, L);
+    allreduce(a, 1, parity, L, vlds);
     HOSCF_MARK(3);
     const double den = normJ + fabs(sigma);
     const bool zero = !(den > 0.0);  // J = 0: T vanishes on the current factors
@@ -512,21 +563,23 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     double rho = 0.0;
     if (!done) {
         for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
-            V[r] = a.x[r] * inv_sqrtN;
+            st_ag(V + r, a.x[r] * inv_sqrtN);
             w[r] = a.g[r] * inv_sqrtN;  // J x~ = [g_n] / sqrt(N)
         }
         grid_barrier(a.bar, a.nwg, &L.timeout);  // V_0 complete before any matvec reads it
         bool stop = false;
         for (int j = 0; j < kmax && !stop; ++j) {
             if (j > 0) {
-                matvec_rows<B>(a, V + (size_t)j * D, w, inv_n1, false, r_lo, r_hi, vlds);
+                matvec_rows<B, true>(a, V + (size_t)j * D, w, inv_n1, false, r_lo, r_hi, vlds);
                 __syncthreads();
                 if (j == 1) HOSCF_MARK(5);
             }
             // pass 1: h_i = V_i . w over own rows
             own_dots(V, w, D, j, r_lo, r_hi, L.mine);
-            allreduce(a, j + 1, parity, L);
+            allreduce(a, j + 1, parity, L, vlds);
+            if (j == 1) HOSCF_MARK(10);
             own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+            if (j == 1) HOSCF_MARK(11);
             if (tid == 0) L.al[j] = L.hsum[j];
             __syncthreads();
             // pass 2: h'_i and ||w||^2
@@ -535,7 +588,8 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
             nn = wg_sum(nn, L.red4);
             if (tid == 0) L.mine[j + 1] = nn;
-            allreduce(a, j + 2, parity, L);
+            allreduce(a, j + 2, parity, L, vlds);
+            if (j == 1) HOSCF_MARK(12);
             double corr2 = 0.0;
             for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
             const double beta = sqrt(fmax(L.hsum[j + 1] - corr2, 0.0));
@@ -598,10 +652,11 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 __syncthreads();
                 stop = L.stop != 0;
             }
+            if (j == 1) HOSCF_MARK(13);
             if (!stop) {
                 const double ib = 1.0 / beta;
                 double* Vn = V + (size_t)(j + 1) * D;
-                for (int64_t r = r_lo + tid; r < r_hi; r += BS) Vn[r] = w[r] * ib;
+                for (int64_t r = r_lo + tid; r < r_hi; r += BS) st_ag(Vn + r, w[r] * ib);
                 grid_barrier(a.bar, a.nwg, &L.timeout);
             }
             if (j == 0) HOSCF_MARK(4);
@@ -639,34 +694,24 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     if (accept) {
         // y = V_m s (own rows), then per-block norm and largest-|entry|
         const int N = a.N;
-        double nrm2[kMaxOrder], best[kMaxOrder], bval[kMaxOrder];
-        int64_t bidx[kMaxOrder];
-        for (int n = 0; n < N; ++n) {
-            nrm2[n] = 0.0;
-            best[n] = -1.0;
-            bval[n] = 0.0;
-            bidx[n] = INT64_MAX;
-        }
         own_combine(V, D, m, r_lo, r_hi, L.s, L.part, w, false);
-        for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
-            const double y = w[r];
-            int n = 0;
-            while (r >= L.xoff[n + 1]) ++n;
-            nrm2[n] = fma(y, y, nrm2[n]);
-            const double ay = fabs(y);
-            if (ay > best[n]) {  // a thread visits rows in increasing order: first max wins
-                best[n] = ay;
-                bval[n] = y;
-                bidx[n] = r;
-            }
-        }
         __shared__ double wbv[BS / 64], wbs[BS / 64];
         __shared__ int64_t wbi[BS / 64];
         for (int n = 0; n < N; ++n) {
-            const double sn = wg_sum(nrm2[n], L.red4);
-            double bv = best[n];
-            int64_t bi = bidx[n];
-            double bs = bval[n];
+            const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
+            const int64_t hi = r_hi < L.xoff[n + 1] ? r_hi : L.xoff[n + 1];
+            double s2 = 0.0, bv = -1.0, bs = 0.0;
+            int64_t bi = INT64_MAX;
+            for (int64_t r = lo + tid; r < hi; r += BS) {  // increasing rows: first max wins
+                const double y = w[r];
+                s2 = fma(y, y, s2);
+                if (fabs(y) > bv) {
+                    bv = fabs(y);
+                    bs = y;
+                    bi = r;
+                }
+            }
+            const double sn = wg_sum(s2, L.red4);
             for (int k = 32; k >= 1; k >>= 1) {
                 const double ov = __shfl_xor(bv, k);
                 const int64_t oi = __shfl_xor(bi, k);
@@ -711,18 +756,19 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         } else {
             double* buf = a.red + (size_t)parity * a.nwg * a.RK;
             parity ^= 1;
-            for (int k = tid; k < 4 * N; k += BS) buf[(size_t)blockIdx.x * a.RK + k] = L.mine[k];
+            for (int k = tid; k < 4 * N; k += BS) st_ag(buf + (size_t)blockIdx.x * a.RK + k, L.mine[k]);
             grid_barrier(a.bar, a.nwg, &L.timeout);
             if (tid == 0) {
                 for (int n = 0; n < N; ++n) {
                     double sn = 0.0, v = -1.0, sg = 0.0, ix = 1e300;
                     for (int wg = 0; wg < a.nwg; ++wg) {
                         const double* p = buf + (size_t)wg * a.RK + 4 * n;
-                        sn += p[0];
-                        if (p[1] > v || (p[1] == v && p[2] < ix)) {
-                            v = p[1];
-                            ix = p[2];
-                            sg = p[3];
+                        const double p0 = ld_ag(p), p1 = ld_ag(p + 1), p2 = ld_ag(p + 2), p3 = ld_ag(p + 3);
+                        sn += p0;
+                        if (p1 > v || (p1 == v && p2 < ix)) {
+                            v = p1;
+                            ix = p2;
+                            sg = p3;
                         }
                     }
                     L.hsum[2 * n] = sn;
@@ -731,27 +777,32 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             }
             __syncthreads();
         }
-        double fl[kMaxOrder], inv[kMaxOrder];
-        bool degenerate = false;
-        double f0 = 1.0;
-        for (int n = 0; n < N; ++n) {
-            const double sn = L.hsum[2 * n];
-            if (!(sn > 0.0)) degenerate = true;
-            inv[n] = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;
-            fl[n] = 1.0;
-            if (a.canonical && n >= 1 && L.hsum[2 * n + 1] < 0.0) {
-                fl[n] = -1.0;
-                f0 = -f0;
+        // flips (sign representative) and inverse block norms, then the iterate
+        if (tid == 0) {
+            bool degenerate = false;
+            double f0 = 1.0;
+            for (int n = 0; n < N; ++n) {
+                const double sn = L.hsum[2 * n];
+                if (!(sn > 0.0)) degenerate = true;
+                L.inv[n] = sn > 0.0 ? 1.0 / sqrt(sn) : 0.0;
+                L.fl[n] = 1.0;
+                if (a.canonical && n >= 1 && L.hsum[2 * n + 1] < 0.0) {
+                    L.fl[n] = -1.0;
+                    f0 = -f0;
+                }
             }
+            L.fl[0] = f0;
+            L.ok = degenerate ? 0 : 1;
         }
-        fl[0] = f0;
-        if (degenerate) {
+        __syncthreads();
+        if (!L.ok) {
             if (blockIdx.x == 0 && tid == 0) a.st->degenerate = 1;
         } else {
-            for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
-                int n = 0;
-                while (r >= L.xoff[n + 1]) ++n;
-                a.x[r] = fl[n] * w[r] * inv[n];
+            for (int n = 0; n < N; ++n) {
+                const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
+                const int64_t hi = r_hi < L.xoff[n + 1] ? r_hi : L.xoff[n + 1];
+                const double f = L.fl[n] * L.inv[n];
+                for (int64_t r = lo + tid; r < hi; r += BS) a.x[r] = f * w[r];
             }
             if (blockIdx.x == 0 && tid == 0 && a.mode == kPostRqi) a.st->accepted = 1;
         }
