@@ -191,11 +191,33 @@ int hoscf_ttvc_backward(const hoscf_tensor* T, const double* x, const void* bloc
  *          (1) the three-output TTVc kernel launches only (all recursion
  *          levels), (2) the level-1 TTVc kernel launch alone (the pass that
  *          streams T from HBM).
+ *   tiling [6] host (optional, NULL = the tile table's choice): workgroups
+ *          the grid is sized for (0 = resident capacity), the smallest p-range
+ *          per workgroup, lanes per tensor row (0 = widest), 1 for
+ *          cache-line-aligned q-chunks (0 = equal chunks), rows per lane group
+ *          (0 = the format's default) and waves per workgroup (4 or 8); used by
+ *          the autotuner.
  *   out_bytes [1] host (optional): algorithmic bytes of T per sweep.
+ * The workspace must be sized by hoscf_workspace_size(HOSCF_OP_TTVC, ...) x 2
+ * when `tiling` is given (a finer split needs more partial-sum space).
  * Synchronises `stream`.
  */
 int hoscf_profile_sweep(const hoscf_tensor* T, const double* x, void* blocks, double* g, int reps,
-                        double* out_ms, int64_t* out_bytes, void* ws, size_t ws_bytes, void* stream);
+                        const int64_t* tiling, double* out_ms, int64_t* out_bytes, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/*
+ * hoscf_tune_set -- registers the level-1 tiling (the tiling[6] of
+ * hoscf_profile_sweep) for tensors of T's dtype and dims; later plans for
+ * that exact shape use it instead of the built-in rule.  tiling = NULL
+ * removes the entry.  Only T->dtype, order and dims are read.  Process-wide
+ * and thread-safe.  Returns HOSCF_INVALID_ARG for an unknown dtype or order,
+ * lanes per row that are not a power of two <= 64, or waves per workgroup
+ * other than 0, 4 or 8.  Written by the autotuner.
+ * hoscf_tune_clear -- removes every registered tiling.
+ */
+int hoscf_tune_set(const hoscf_tensor* T, const int64_t* tiling);
+void hoscf_tune_clear(void);
 
 /* ---- batched form: many small order-3 tensors, greedy rank-R deflation ---- */
 

@@ -77,9 +77,10 @@ struct SolveLayout {
     size_t used = 0;
     bool ok = false;
 
-    bool build(const hoscf_tensor& T, void* blocks_out, bool solve, int kmax, void* ws, size_t ws_bytes) {
+    bool build(const hoscf_tensor& T, void* blocks_out, bool solve, int kmax, void* ws, size_t ws_bytes,
+               const int64_t* tiling = nullptr) {
         Arena ar(ws, ws_bytes);
-        const SweepTuning tune = lookup_tuning(T);
+        const SweepTuning tune = tiling ? tuning_from(tiling) : lookup_tuning(T);
         st = ar.take<SolveState>(1);
         two_phase = solve && (T.dtype == HOSCF_BF16 || T.dtype == HOSCF_FP8E4M3) && T.data_f32 != nullptr;
         sweep.build(T, T.dtype, T.data, T.dtype == HOSCF_FP8E4M3 ? T.scale : 1.f, blocks_out, ar, tune);
@@ -149,11 +150,12 @@ int hoscf_ttvc(const hoscf_tensor* T, const double* x, void* blocks, double* g, 
     return HOSCF_OK;
 }
 
-int hoscf_profile_sweep(const hoscf_tensor* T, const double* x, void* blocks, double* g, int reps, double* out_ms,
-                        int64_t* out_bytes, void* ws, size_t ws_bytes, void* stream) {
+int hoscf_profile_sweep(const hoscf_tensor* T, const double* x, void* blocks, double* g, int reps,
+                        const int64_t* tiling, double* out_ms, int64_t* out_bytes, void* ws, size_t ws_bytes,
+                        void* stream) {
     if (!valid_tensor(T) || !x || !blocks || !g || !out_ms || reps < 1) return HOSCF_INVALID_ARG;
     SolveLayout lay;
-    if (!ws || !lay.build(*T, blocks, false, 1, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
+    if (!ws || !lay.build(*T, blocks, false, 1, ws, ws_bytes, tiling)) return HOSCF_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nn = std::max(1, lay.sweep.num_nodes());
     std::vector<hipEvent_t> ev(2 * nn + 2);

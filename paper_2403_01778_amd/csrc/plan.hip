@@ -39,7 +39,7 @@ void SweepPlan::add_node(int fmt, const void* in, const int* modes, int k, float
 
     Node nd{};
     nd.fmt = fmt;
-    nd.sh = ttvc3_shape(fmt, P, M, Q, tune.target_waves, tune.bp_min);
+    nd.sh = ttvc3_shape(fmt, P, M, Q, tune);
     Ttvc3Args& a = nd.a;
     a.T = in;
     a.P = P;
@@ -99,8 +99,8 @@ void SweepPlan::add_node(int fmt, const void* in, const int* modes, int k, float
     nodes_.push_back(nd);
     shapes.push_back(nd.sh);
     const int accfmt = f64 ? HOSCF_F64 : HOSCF_F32;
-    if (a.doL && k - 1 >= 3) add_node(accfmt, Ldst, modes, k - 1, 1.f, needL, ar, tune);
-    if (a.doR && k - 1 >= 3) add_node(accfmt, Rdst, modes + 1, k - 1, 1.f, needR, ar, tune);
+    if (a.doL && k - 1 >= 3) add_node(accfmt, Ldst, modes, k - 1, 1.f, needL, ar, tune.inner());
+    if (a.doR && k - 1 >= 3) add_node(accfmt, Rdst, modes + 1, k - 1, 1.f, needR, ar, tune.inner());
 }
 
 bool SweepPlan::build(const hoscf_tensor& T, int fmt, const void* data, float scale, void* blocks_out,

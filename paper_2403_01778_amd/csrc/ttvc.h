@@ -26,7 +26,7 @@ struct Ttvc3Args {
 };
 
 struct Ttvc3Shape {
-    int VEC = 1, LR = 64, MB = 16, QW = 64, QWe = 64;
+    int VEC = 1, LR = 64, MB = 16, QW = 64, QWe = 64, NW = 4;
     int nq = 1;
     int64_t nmt = 1, npt = 1, BP = 1;
     int64_t grid() const { return (int64_t)nq * nmt * npt; }
@@ -58,11 +58,25 @@ struct TransposeArgs {
 
 // Tiling parameters a sweep plan uses (filled from the tile table).
 struct SweepTuning {
-    int64_t target_waves = 0;  // 0: size the grid from resident workgroups
+    int64_t target_wg = 0;     // workgroups the grid is sized for; 0: resident capacity
     int64_t bp_min = 8;
+    int lr = 0;                // lanes per row (power of two <= 64); 0: widest that fits a row
+    int align = 1;             // 1: q-chunks are whole 128-byte lines (last one ragged);
+                               // 0: equal q-chunks (edges may split lines)
+    int mb = 0;                // rows per lane group (the format's default, or half of it)
+    int nw = 0;                // waves per workgroup (4 or 8)
+    // recursion levels (their inputs are the small L/R intermediates, not T):
+    // widest rows, the format's rows per lane group, 8 waves
+    SweepTuning inner() const {
+        SweepTuning t = *this;
+        t.lr = 0;
+        t.mb = 0;
+        t.nw = 8;
+        return t;
+    }
 };
 
-Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, int64_t target_waves, int64_t bp_min);
+Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, const SweepTuning& tune);
 hipError_t launch_ttvc3(int fmt, const Ttvc3Shape& sh, const Ttvc3Args& a, hipStream_t s);
 hipError_t launch_reduce(bool f64, const ReduceJobs& jobs, int njobs, hipStream_t s);
 hipError_t launch_prep(bool f64, const double* x, int N, const FactorOffsets& off, double* xu, void* xa,

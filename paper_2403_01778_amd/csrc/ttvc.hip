@@ -142,21 +142,38 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 // ---------------------------------------------------------------------------
 // K1: the three-output streaming kernel.
 // ---------------------------------------------------------------------------
-template <int FMT, int VEC, int LR, int MB>
-__global__ __launch_bounds__(256) void ttvc3_kernel(Ttvc3Args args) {
+template <int FMT, int VEC, int LR, int MB, int NW = 4>
+__global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     using L = Loader<FMT, VEC>;
     using A = typename Fmt<FMT>::A;
     using S = typename Fmt<FMT>::S;
     constexpr int G = 64 / LR;              // rows per wave instruction
     constexpr int QW = LR * VEC;            // q-chunk width
     constexpr int WM = G * MB;              // rows of one wave's m-tile
-    constexpr int KS = (32768 / (256 * VEC * (int)sizeof(A))) > 0 ? (32768 / (256 * VEC * (int)sizeof(A))) : 1;
-    __shared__ A cbuf[KS * 4 * G * QW];     // = KS * 256 * VEC values
+    constexpr int NT = NW * 64;             // threads per workgroup
+    constexpr int KS = (32768 / (NT * VEC * (int)sizeof(A))) > 0 ? (32768 / (NT * VEC * (int)sizeof(A))) : 1;
+    __shared__ A cbuf[KS * NW * G * QW];    // = KS * NT * VEC values
+    // Flushes every KS slabs: all waves sum the C contributions into cres,
+    // then ONE wave (rotating) writes the combined C rows and the buffered L
+    // rows to global memory.  Loads and stores share one completion counter,
+    // so only the storing wave waits for its stores; the other waves keep
+    // their prefetched slabs in flight.  L values of the workgroup's 4*WM rows
+    // are kept per flush (double-buffered) and written as whole rows.
+    constexpr bool LBUF = 2 * KS * NW * WM * (int)sizeof(A) <= 16384;
+    __shared__ A lbuf[LBUF ? 2 * KS * NW * WM : 1];
+    __shared__ A cres[2 * KS * QW];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane / LR, c = lane % LR;
     const int64_t P = args.P, M = args.M, Q = args.Q;
+    // Workgroups are dealt round-robin to the 8 XCDs.  Renumber them so that
+    // consecutive tile ids (the q-chunks of the same rows, which share the
+    // cache lines at their edges) run on the same XCD and meet in its L2.
     int64_t bid = blockIdx.x;
+    {
+        const int64_t G8 = (int64_t)gridDim.x / 8 * 8;
+        if (bid < G8) bid = (bid % 8) * (G8 / 8) + bid / 8;
+    }
     const int qc = (int)(bid % args.nq);
     bid /= args.nq;
     const int64_t mtw = bid % args.nmt;
@@ -164,7 +181,7 @@ __global__ __launch_bounds__(256) void ttvc3_kernel(Ttvc3Args args) {
 
     const int64_t q0 = (int64_t)qc * args.QWe + (int64_t)c * VEC;
     const bool qok = (c * VEC < args.QWe) && (q0 < Q);
-    const int64_t mrow0 = (mtw * 4 + wave) * WM + g;
+    const int64_t mrow0 = (mtw * NW + wave) * WM + g;
     const int64_t p0 = pt * args.BP;
     const int64_t p1 = p0 + args.BP < P ? p0 + args.BP : P;
     const A* xp = static_cast<const A*>(args.xp);
@@ -193,13 +210,10 @@ __global__ __launch_bounds__(256) void ttvc3_kernel(Ttvc3Args args) {
     A* Lout = static_cast<A*>(args.L);
     A* Rout = static_cast<A*>(args.R);
     A* Cout = static_cast<A*>(args.C);
-    int slot = 0;
-    for (int64_t p = p0; p < p1; ++p) {
+    int slot = 0, par = 0, nflush = 0;
+    // Body of one p-slab: R, C and the row dots for L from MB rows in `raw`.
+    auto body = [&](const typename L::Raw* raw, int64_t p) {
         const A xpp = xp[p];
-        const S* rowp = Tb + (p * M + mrow0) * Q + q0;
-        typename L::Raw raw[MB];
-#pragma unroll
-        for (int i = 0; i < MB; ++i) raw[i] = rok[i] ? L::load(rowp + (int64_t)i * G * Q) : L::zero();
         A accC[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) accC[v] = A(0);
@@ -226,32 +240,80 @@ __global__ __launch_bounds__(256) void ttvc3_kernel(Ttvc3Args args) {
             if ((c & ((1 << FULL) - 1)) == 0) {
 #pragma unroll
                 for (int j = 0; j < NR; ++j) {
-                    const int64_t m = mrow0 + (int64_t)G * (base + j);
-                    if (m < M) Lout[((int64_t)qc * P + p) * M + m] = dl[j] * scale;
+                    const int rl = g + G * (base + j);  // row within the wave's m-tile
+                    if constexpr (LBUF) {
+                        lbuf[(par * KS + slot) * NW * WM + wave * WM + rl] = dl[j];
+                    } else {
+                        const int64_t m = mrow0 - g + rl;
+                        if (m < M) Lout[((int64_t)qc * P + p) * M + m] = dl[j] * scale;
+                    }
                 }
             }
         }
         if (args.doC) {
-            A* dst = cbuf + ((slot * 4 + wave) * G + g) * QW + c * VEC;
+            A* dst = cbuf + ((slot * NW + wave) * G + g) * QW + c * VEC;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) dst[v] = accC[v];
+        }
+        if (args.doC || (LBUF && args.doL)) {
             ++slot;
             if (slot == KS || p == p1 - 1) {
                 __syncthreads();
-                const int nval = slot * QW;
-                for (int idx = tid; idx < nval; idx += 256) {
-                    const int s = idx / QW, qi = idx - s * QW;
-                    const A* src = cbuf + (s * 4 * G) * QW + qi;
-                    A sum = A(0);
-                    for (int k = 0; k < 4 * G; ++k) sum += src[k * QW];
-                    const int64_t q = (int64_t)qc * args.QWe + qi;
-                    const int64_t pp = p - slot + 1 + s;
-                    if (qi < args.QWe && q < Q) Cout[(mtw * P + pp) * Q + q] = sum * scale;
+                if (args.doC) {
+                    const int nval = slot * QW;
+                    for (int idx = tid; idx < nval; idx += NT) {
+                        const int s = idx / QW, qi = idx - s * QW;
+                        const A* src = cbuf + (s * NW * G) * QW + qi;
+                        A sum = A(0);
+                        for (int k = 0; k < NW * G; ++k) sum += src[k * QW];
+                        cres[par * KS * QW + idx] = sum * scale;
+                    }
                 }
                 __syncthreads();
+                {
+                    if (args.doC) {
+                        const int nval = slot * QW;
+                        for (int idx = tid; idx < nval; idx += NT) {
+                            const int s = idx / QW, qi = idx - s * QW;
+                            const int64_t q = (int64_t)qc * args.QWe + qi;
+                            const int64_t pp = p - slot + 1 + s;
+                            if (qi < args.QWe && q < Q)
+                                __builtin_nontemporal_store(cres[par * KS * QW + idx], Cout + (mtw * P + pp) * Q + q);
+                        }
+                    }
+                    if constexpr (LBUF) {
+                        if (args.doL) {
+                            const int nval = slot * NW * WM;
+                            for (int idx = tid; idx < nval; idx += NT) {
+                                const int s = idx / (NW * WM), k = idx - s * (NW * WM);
+                                const int64_t m = mtw * NW * WM + k;
+                                const int64_t pp = p - slot + 1 + s;
+                                if (m < M) Lout[((int64_t)qc * P + pp) * M + m] = lbuf[par * KS * NW * WM + idx] * scale;
+                            }
+                        }
+                    }
+                }
+                ++nflush;
+                par ^= 1;
                 slot = 0;
             }
         }
+    };
+    auto fetch = [&](typename L::Raw* raw, int64_t p) {
+        const S* rowp = Tb + (p * M + mrow0) * Q + q0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) raw[i] = rok[i] ? L::load(rowp + (int64_t)i * G * Q) : L::zero();
+    };
+    // Two register buffers: the rows of slab p + 1 are requested before slab p
+    // is consumed, so each wave keeps a full slab of loads in flight.
+    typename L::Raw buf0[MB], buf1[MB];
+    if (p0 < p1) fetch(buf0, p0);
+    for (int64_t p = p0; p < p1; p += 2) {
+        if (p + 1 < p1) fetch(buf1, p + 1);
+        body(buf0, p);
+        if (p + 1 >= p1) break;
+        if (p + 2 < p1) fetch(buf0, p + 2);
+        body(buf1, p + 1);
     }
     if (args.doR) {
 #pragma unroll
@@ -382,22 +444,24 @@ static int pow2_at_least(int64_t v) {
     return p;
 }
 
-template <int FMT, int VEC, int MB>
+// Rows per lane-group for each storage format (register budget of R).
+template <int FMT> constexpr int mb_vec() { return FMT == HOSCF_F64 ? 16 : FMT == HOSCF_F32 ? 16 : FMT == HOSCF_BF16 ? 8 : 4; }
+
+template <int FMT, int VEC, int MB, int NW>
 static hipError_t launch_lr(int LR, dim3 grid, const Ttvc3Args& a, hipStream_t s) {
+    const dim3 blk(NW * 64);
+    constexpr bool base = (MB == mb_vec<FMT>() && NW == 4);
     switch (LR) {
-        case 1: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 1, MB>), grid, dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 2, MB>), grid, dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 4, MB>), grid, dim3(256), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 8, MB>), grid, dim3(256), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 16, MB>), grid, dim3(256), 0, s, a); break;
-        case 32: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 32, MB>), grid, dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 64, MB>), grid, dim3(256), 0, s, a); break;
+        case 1: if constexpr (base) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 1, MB, NW>), grid, blk, 0, s, a); break;
+        case 2: if constexpr (base) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 2, MB, NW>), grid, blk, 0, s, a); break;
+        case 4: if constexpr (base) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 4, MB, NW>), grid, blk, 0, s, a); break;
+        case 8: if constexpr (NW == 4) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 8, MB, NW>), grid, blk, 0, s, a); break;
+        case 16: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 16, MB, NW>), grid, blk, 0, s, a); break;
+        case 32: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 32, MB, NW>), grid, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 64, MB, NW>), grid, blk, 0, s, a); break;
     }
     return hipGetLastError();
 }
-
-// Rows per lane-group for each storage format (register budget of R).
-template <int FMT> constexpr int mb_vec() { return FMT == HOSCF_F64 ? 16 : FMT == HOSCF_F32 ? 16 : FMT == HOSCF_BF16 ? 8 : 4; }
 
 // Resident workgroups of the three-output kernel per CU (register-limited),
 // and the CU count, for grid sizing.
@@ -440,7 +504,8 @@ static int resident_slots(int fmt, int VEC, int LR) {
     return c;
 }
 
-Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, int64_t target_waves, int64_t bp_min) {
+Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, const SweepTuning& tune) {
+    const int64_t target_wg = tune.target_wg, bp_min = tune.bp_min;
     Ttvc3Shape s;
     static const int vecs[4] = {2, 4, 8, 16};
     static const int mbs[4] = {16, 16, 8, 4};
@@ -448,20 +513,30 @@ Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, int64_t target_
     s.VEC = (Q % vecs[fmt] == 0) ? vecs[fmt] : 1;
     s.MB = s.VEC > 1 ? mbs[fmt] : 16;
     s.LR = s.VEC > 1 ? pow2_at_least((Q + s.VEC - 1) / s.VEC) : 64;
+    if (s.VEC > 1 && tune.lr > 0 && tune.lr < s.LR) s.LR = tune.lr;
     if (s.LR < 1) s.LR = 1;
+    if (s.VEC > 1 && s.LR >= 8 && tune.mb == mbs[fmt] / 2) s.MB = mbs[fmt] / 2;
+    s.NW = (s.VEC > 1 && s.LR >= 16 && tune.nw == 8) ? 8 : 4;
     const int G = 64 / s.LR;
     s.QW = s.LR * s.VEC;
     s.nq = (int)((Q + s.QW - 1) / s.QW);
-    // equal q-chunks: ceil(Q / nq) rounded up to whole vectors
-    const int64_t per_chunk = (Q + s.nq - 1) / s.nq;
-    s.QWe = (int)(((per_chunk + s.VEC - 1) / s.VEC) * s.VEC);
+    if (tune.align || s.nq == 1) {
+        // chunks of QW elements (whole cache lines when QW * esz is a multiple
+        // of 128 bytes); the last chunk is ragged
+        s.QWe = s.QW;
+    } else {
+        // equal q-chunks: ceil(Q / nq) rounded up to whole vectors
+        const int64_t per_chunk = (Q + s.nq - 1) / s.nq;
+        s.QWe = (int)(((per_chunk + s.VEC - 1) / s.VEC) * s.VEC);
+    }
     const int64_t wm = (int64_t)G * s.MB;
     const int64_t nmt_w = (M + wm - 1) / wm;
-    s.nmt = (nmt_w + 3) / 4;
+    s.nmt = (nmt_w + s.NW - 1) / s.NW;
     const int64_t cols = (int64_t)s.nq * s.nmt;
     // p-split: balance rounds of resident workgroups against the R partials it
     // creates (npt copies of M x Q accumulators, written and read back).
-    const int64_t slots = target_waves > 0 ? std::max<int64_t>(1, target_waves / 4) : resident_slots(fmt, s.VEC, s.LR);
+    const int64_t slots = target_wg > 0 ? target_wg
+                                        : std::max<int64_t>(1, resident_slots(fmt, s.VEC, s.LR) * 4 / s.NW);
     const double tbytes = (double)P * (double)M * (double)Q * esz[fmt];
     const double accb = fmt == HOSCF_F64 ? 8.0 : 4.0;
     double best = 1e300;
@@ -491,7 +566,12 @@ static hipError_t launch_ttvc3_fmt(const Ttvc3Shape& sh, const Ttvc3Args& a, hip
     const dim3 grid((unsigned)((int64_t)sh.nq * sh.nmt * sh.npt));
     constexpr int V = Fmt<FMT>::VEC;
     constexpr int MBV = mb_vec<FMT>();
-    if (sh.VEC == V) return launch_lr<FMT, V, MBV>(sh.LR, grid, a, s);
+    if (sh.VEC == V) {
+        const bool half = sh.MB == MBV / 2 && sh.LR >= 8;
+        if (sh.NW == 8 && sh.LR >= 16)
+            return half ? launch_lr<FMT, V, MBV / 2, 8>(sh.LR, grid, a, s) : launch_lr<FMT, V, MBV, 8>(sh.LR, grid, a, s);
+        return half ? launch_lr<FMT, V, MBV / 2, 4>(sh.LR, grid, a, s) : launch_lr<FMT, V, MBV, 4>(sh.LR, grid, a, s);
+    }
     hipLaunchKernelGGL((ttvc3_kernel<FMT, 1, 64, 16>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -63,9 +63,13 @@ _lib.hoscf_ttvc_backward.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, _P
                                      ctypes.c_int, _P, _P, ctypes.c_size_t, _P]
 _lib.hoscf_ttvc_backward.restype = ctypes.c_int
 _lib.hoscf_profile_sweep.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, ctypes.c_int,
-                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _P,
-                                     ctypes.c_size_t, _P]
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64), _P, ctypes.c_size_t, _P]
 _lib.hoscf_profile_sweep.restype = ctypes.c_int
+_lib.hoscf_tune_set.argtypes = [ctypes.POINTER(HoscfTensor), ctypes.POINTER(ctypes.c_int64)]
+_lib.hoscf_tune_set.restype = ctypes.c_int
+_lib.hoscf_tune_clear.argtypes = []
+_lib.hoscf_tune_clear.restype = None
 _lib.hoscf_batch_plan_create.argtypes = [ctypes.c_int, ctypes.POINTER(HoscfTensor), ctypes.c_int,
                                          ctypes.POINTER(HoscfOptions), ctypes.POINTER(ctypes.c_void_p)]
 _lib.hoscf_batch_plan_create.restype = ctypes.c_int
@@ -173,9 +177,14 @@ def ttvc(T: torch.Tensor, x: torch.Tensor, scale: float = 1.0) -> TtvcResult:
     return TtvcResult(unpack_blocks(blocks, dims), blocks, g, float(s[0]), float(s[1]), float(s[2]), sc)
 
 
-def profile_sweep(T: torch.Tensor, x: torch.Tensor, reps: int = 10, scale: float = 1.0):
+def profile_sweep(T: torch.Tensor, x: torch.Tensor, reps: int = 10, scale: float = 1.0, tiling=None,
+                  return_outputs: bool = False):
     """HIP-event timings (ms per sweep) of a sweep: (whole sweep, all TTVc
-    kernel launches, level-1 TTVc launch) and the algorithmic bytes of T."""
+    kernel launches, level-1 TTVc launch) and the algorithmic bytes of T.
+    tiling = (workgroups the grid is sized for, smallest p-range, lanes per
+    row, aligned q-chunks, rows per lane group, waves per workgroup)
+    overrides the tile table.  With return_outputs the packed blocks and g of
+    the last sweep follow."""
     desc = describe(T, scale)
     dims = list(T.shape)
     bdt = torch.float64 if T.dtype == torch.float64 else torch.float32
@@ -183,12 +192,39 @@ def profile_sweep(T: torch.Tensor, x: torch.Tensor, reps: int = 10, scale: float
     blocks = torch.empty(nb, dtype=bdt, device=T.device)
     g = torch.empty(sum(dims), dtype=torch.float64, device=T.device)
     x = x.to(device=T.device, dtype=torch.float64).contiguous()
-    ws = _workspace(workspace_size(OP_TTVC, desc), T.device)
+    need = workspace_size(OP_TTVC, desc)
+    tl = None
+    if tiling is not None:
+        tl = _tiling6(tiling)
+        need = 3 * need + (256 << 20)
+    ws = _workspace(need, T.device)
     out = (ctypes.c_double * 3)()
     nbytes = ctypes.c_int64(0)
-    _check(_lib.hoscf_profile_sweep(ctypes.byref(desc), x.data_ptr(), blocks.data_ptr(), g.data_ptr(), int(reps), out,
-                                    ctypes.byref(nbytes), ws.data_ptr(), ws.numel(), _stream()), "hoscf_profile_sweep")
-    return float(out[0]), float(out[1]), float(out[2]), int(nbytes.value)
+    _check(_lib.hoscf_profile_sweep(ctypes.byref(desc), x.data_ptr(), blocks.data_ptr(), g.data_ptr(), int(reps), tl,
+                                    out, ctypes.byref(nbytes), ws.data_ptr(), ws.numel(), _stream()),
+           "hoscf_profile_sweep")
+    res = (float(out[0]), float(out[1]), float(out[2]), int(nbytes.value))
+    return res + (blocks, g) if return_outputs else res
+
+
+def _tiling6(tiling) -> "ctypes.Array":
+    t6 = list(tiling) + [8, 0, 1, 0, 4][len(tiling) - 1:]
+    return (ctypes.c_int64 * 6)(*[int(v) for v in t6[:6]])
+
+
+def tune_set(dtype: int, dims: Sequence[int], tiling=None) -> None:
+    """Register the level-1 tiling for tensors of this storage dtype and
+    dims (None removes the entry); see profile_sweep for the fields."""
+    desc = HoscfTensor()
+    desc.order = len(dims)
+    for i, d in enumerate(dims):
+        desc.dims[i] = int(d)
+    desc.dtype = int(dtype)
+    _check(_lib.hoscf_tune_set(ctypes.byref(desc), None if tiling is None else _tiling6(tiling)), "hoscf_tune_set")
+
+
+def tune_clear() -> None:
+    _lib.hoscf_tune_clear()
 
 
 @dataclass

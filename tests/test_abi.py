@@ -85,3 +85,16 @@ def test_invalid_arguments_rejected_without_launch(lib):
     assert so.hoscf_solve(ctypes.byref(good), 0x10, ctypes.byref(opts), 0x10, ctypes.byref(sig), ctypes.byref(info),
                           0x10, 1 << 30, None) == lib.INVALID_ARG
     assert so.hoscf_quantize(0x10, 10, 1, 0x10, 0x10, 0x10, 256, None) == lib.INVALID_ARG
+
+
+def test_tune_table_validation(lib):
+    """hoscf_tune_set checks the tiling on the host (no GPU needed)."""
+    dims = (11, 12, 13)
+    lib.tune_set(lib.F32, dims, (0, 1, 32, 1, 8, 8))
+    lib.tune_set(lib.F32, dims, None)
+    for bad in [(0, 1, 12, 1, 8, 8), (0, 1, 128, 1, 8, 8), (0, 1, 32, 2, 8, 8), (0, 1, 32, 1, 8, 6), (-1, 1, 32, 1, 8, 4)]:
+        with pytest.raises(lib.HoscfError):
+            lib.tune_set(lib.F32, dims, bad)
+    with pytest.raises(lib.HoscfError):
+        lib.tune_set(7, dims, (0, 1, 32, 1, 8, 8))
+    lib.tune_clear()

@@ -70,6 +70,61 @@ def test_ttvc_order_n(lib, dims, dtype):
     _check_against_oracle(lib, Tt, x)
 
 
+def _check_outputs(Tnp, x, flat, g, tol):
+    """Blocks (packed) and g of a sweep against the oracle, entrywise bound."""
+    import paper_2403_01778_amd.hoscf as H
+    dims = list(Tnp.shape)
+    xs = oracle.normalize_blocks(x, dims)
+    ref = oracle.sweep(Tnp, xs)
+    absb = oracle.blocks(np.abs(Tnp), [np.abs(v) for v in xs])
+    blks = H.unpack_blocks(flat, dims)
+    for k, (key, A_ref) in enumerate(ref.blocks.items()):
+        A = blks[k].double().cpu().numpy()
+        err = np.abs(A - A_ref)
+        assert np.all(err <= tol * absb[key] + 1e-300), (key, float(np.max(err / (absb[key] + 1e-300))))
+    g_ref = oracle.stack(oracle.mode_vectors(Tnp, xs))
+    g_abs = oracle.stack(oracle.mode_vectors(np.abs(Tnp), [np.abs(v) for v in xs]))
+    assert np.all(np.abs(g.cpu().numpy() - g_ref) <= tol * g_abs + 1e-300)
+
+
+@pytest.mark.parametrize("dims", [(70, 90, 300), (20, 24, 28, 256), (9, 10, 11, 12, 64)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_ttvc_every_tiling(lib, dims, dtype):
+    """Every tiling the autotuner may choose (lanes per row, rows per lane
+    group, waves per workgroup) plus forced grid sizes and p-splits gives the
+    oracle's blocks: the tiling changes only the summation order."""
+    from paper_2403_01778_amd import autotune
+    Tt, x = _case(dims, dtype, 3000 + sum(dims))
+    Td = Tt.to(DEV).contiguous()
+    Tnp = Tt.double().numpy()
+    tol = TOL[dtype]
+    code = lib.F64 if dtype == torch.float64 else lib.F32
+    extra = [(7, 1, 0, 0, 0, 4), (1000, 2, 64, 1, 0, 8), (3, 1, 16, 0, 0, 8)]
+    for t in autotune.candidates(code) + extra:
+        print(f"[ttvc-tiling] dims={dims} dtype={dtype} tiling={t}", flush=True)
+        r = lib.profile_sweep(Td, torch.from_numpy(x), reps=1, tiling=t, return_outputs=True)
+        _check_outputs(Tnp, x, r[4], r[5], tol)
+
+
+def test_tune_table_register(lib):
+    """A registered tiling is used by later plans of that shape (the outputs
+    still match the oracle); removing it restores the built-in rule."""
+    from paper_2403_01778_amd import autotune
+    dims = (48, 40, 512)
+    Tt, x = _case(dims, torch.float32, 77)
+    Td = Tt.to(DEV).contiguous()
+    rec = autotune.autotune(Td, torch.from_numpy(x), reps=2)
+    assert rec["tiling"] in [list(t) for t in autotune.candidates(lib.F32)]
+    try:
+        lib.tune_set(lib.F32, dims, (0, 1, 16, 1, 8, 8))
+        r = lib.ttvc(Td, torch.from_numpy(x))
+        _check_outputs(Tt.double().numpy(), x, r.blocks_flat, r.g, TOL[torch.float32])
+    finally:
+        lib.tune_set(lib.F32, dims, None)
+    with pytest.raises(lib.HoscfError):
+        lib.tune_set(lib.F32, dims, (0, 1, 12, 1, 8, 8))
+
+
 def test_ttvc_deterministic(lib):
     Tt, x = _case((150, 140, 270), torch.float32, 7)
     T = Tt.to(DEV)
