@@ -28,6 +28,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+
+# HBM traffic of the level-1 TTVc kernel on this workload, from two
+# rocprofv3 counter passes (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the
+# factors a 1 GiB device copy reads on the same counters); summary in
+# profiles/ttvc3_kernel_800cubed_f32_pmc.md.  Valid only for the kernel source
+# the counters were taken on.
+TRAFFIC = {"kernel_source_sha256": "0c235c976cd7ae24a70d1aabb0e41ac2435386733c34f06340fd852e85573f55",
+           "read_bytes": 2_000_217.8 * 1024, "write_bytes": 85_000.0 * 1024}
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2403_01778_amd", "csrc", "ttvc.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["kernel_source_sha256"]:
+            return None
+    return round(TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"])
 METRIC = "TTVc HBM GB/s (% peak); HOSCF solves/s, chosen vs plain at σ rel err≤1e-6"
 
 
@@ -158,7 +175,7 @@ def main():
         "ttvc_sweep_ms": round(ms_sweep, 4),
         "ttvc_kernels_ms": round(ms_k1, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(),
                      "kernel": "ttvc3_kernel (level-1 pass over T)", "bytes_per_launch": nbytes,
                      "launch_ms": round(ms_root, 5)},
     }

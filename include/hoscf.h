@@ -82,8 +82,8 @@ typedef struct {
 /* Solver options (Algorithm 1 and Section 4.3/4.4). */
 typedef struct {
     int32_t algo;            /* 0 = HOSCF, 1 = iHOSCF */
-    double tol;              /* stop when the residual of eq. stop-3 (read as the NEPv residual at
-                                the iterate, see DESIGN) is <= tol */
+    double tol;              /* stop when the residual of eq. stop-3, read as the NEPv residual
+                                at the iterate with J rebuilt there, is <= tol */
     int32_t max_iter;        /* maximum number of eigen-steps */
     double tol_lp;           /* precision form: low-precision sweeps until residual <= tol_lp */
     int32_t max_refine;      /* precision form: max FP32 refinement iterations (0 = max_iter) */
@@ -154,16 +154,29 @@ int hoscf_quantize(const float* src, int64_t n, int dtype, void* dst, float* sca
 
 /*
  * hoscf_backward -- gradient of a loss L(sigma, u) through hoscf_solve
- * (project addition; derived from eq. kkt by implicit differentiation).
- *   x, sigma  a converged solve's factors and sigma.
- *   g_sigma   dL/dsigma;  g_x [D] FP64 device dL/du (NULL = 0).
- *   grad_T    same shape as T; float (grad_dtype = HOSCF_F32) or double (HOSCF_F64):
- *             dL/dT = g_sigma u_1 o ... o u_N - sum_n u_1 o .. o mu_n o .. o u_N,
- *             with mu tangent (u_n' mu_n = 0) solving P(M - sigma I)P mu = P g_x,
- *             M = (N-1) J(x), P the blockwise projector onto the tangent space.
- *   mu_out    [D] FP64 device, optional (NULL).
- *   info      [2] FP64 device, optional: CG iterations and final relative residual.
- * T is read once (one sweep for the blocks); grad_T is written once.
+ * (project addition; derived from the stationarity conditions, eq. kkt, by
+ * implicit differentiation).
+ *   x        [D] FP64 device: the factors of a converged solve (normalised per
+ *            block on entry, so they need not be exactly unit).
+ *   sigma    the solve's sigma (the shift of the linearised system).
+ *   g_sigma  dL/dsigma;  g_x [D] FP64 device dL/du, or NULL for 0.
+ *   grad_T   device, same shape as T, FP32 (grad_dtype = HOSCF_F32) or FP64
+ *            (HOSCF_F64), overwritten with
+ *              dL/dT = g_sigma u_1 o ... o u_N - sum_n u_1 o .. o mu_n o .. o u_N,
+ *            where mu is tangent (u_n' mu_n = 0) and solves
+ *              P (M - sigma I) P mu = P g_x,
+ *            M = (N-1) J(u) (off-diagonal blocks A_{m,n}, zero diagonal), P the
+ *            blockwise projector onto the tangent space.  Equivalently
+ *            [[M - sigma I, X], [X', 0]] [mu; nu] = [g_x; 0], X = blockdiag(u_n).
+ *            (d sigma / dT = u_1 o ... o u_N by the envelope theorem.)
+ *   mu_out   [D] FP64 device, optional: mu.
+ *   info     [2] FP64 device, optional: Lanczos steps of the projected solve
+ *            and its final relative residual (NaN if it did not reach 1e-12).
+ * Reads T once (one sweep for the blocks at u), solves the projected shifted
+ * system by Lanczos-Galerkin on the blocks, writes grad_T once.  The system is
+ * definite at a strict local maximum; at a degenerate point the result is
+ * whatever the Galerkin solve returns (check info).
+ * Workspace: hoscf_workspace_size(HOSCF_OP_BACKWARD, T, NULL).
  */
 int hoscf_backward(const hoscf_tensor* T, const double* x, double sigma, double g_sigma,
                    const double* g_x, void* grad_T, int grad_dtype, double* mu_out,
@@ -171,15 +184,20 @@ int hoscf_backward(const hoscf_tensor* T, const double* x, double sigma, double 
 
 /*
  * hoscf_ttvc_backward -- adjoint of hoscf_ttvc's differentiable outputs
- * (g, sigma) for cotangents gbar [D] (NULL = 0) and sigma_bar:
+ * g_n = T x_{k != n} u_k and sigma = T(u) (Section 4.2 contractions) for
+ * cotangents gbar [D] FP64 device (NULL = 0) and sigma_bar:
  *   grad_T = sum_n u_1 o .. o gbar_n o .. o u_N + sigma_bar u_1 o ... o u_N
  *   grad_x = the gradient w.r.t. the unit factors u:
  *            grad_x_m = sum_{n != m} A_{m,n} gbar_n + sigma_bar g_m
- * `blocks` and `g` are the forward's outputs at the same x (x unit).
- * grad_T may be NULL (factor adjoint only); grad_x may be NULL.
+ * x is normalised per block on entry.  `blocks`: the packed blocks of
+ * hoscf_ttvc at the same x (FP64 if T is FP64, else FP32), or NULL to
+ * recompute them with one sweep over T.  grad_T (FP32 or FP64 by grad_dtype,
+ * same shape as T) and grad_x ([D] FP64) may each be NULL.  Cotangents on the
+ * J blocks themselves are not supported.
+ * Workspace: hoscf_workspace_size(HOSCF_OP_TTVC_BACKWARD, T, NULL).
  */
 int hoscf_ttvc_backward(const hoscf_tensor* T, const double* x, const void* blocks,
-                        const double* g, const double* gbar, double sigma_bar,
+                        const double* gbar, double sigma_bar,
                         void* grad_T, int grad_dtype, double* grad_x,
                         void* ws, size_t ws_bytes, void* stream);
 

@@ -7,8 +7,7 @@ Notation follows the paper: T is the order-N tensor (the paper's A, order d),
 x_n are the unit factor vectors (u^(n)), sigma is the objective / singular
 value (lambda), and the stacked unit vector x~ = [x_1; ...; x_N] / sqrt(N).
 
-Readings of passages where the paper is silent or garbled (each also listed in
-DESIGN.md):
+Readings of passages where the paper is silent or garbled:
   * J is always built at the latest normalised iterate (Alg. 1 indexing).
   * The stopping test of eq. (stop-3) is the NEPv residual at the iterate with
     J rebuilt there: ||J(x~)x~ - rho x~|| / (||J||_F + |sigma|), rho = sigma.

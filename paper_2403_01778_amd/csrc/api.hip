@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "common.h"
+#include "outer.h"
 #include "post.h"
 #include "quant.h"
 #include "ttvc.h"
@@ -28,6 +29,19 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* x, int64_t 
     const bool flip = st->sigma < 0.0;
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < D; r += (int64_t)gridDim.x * 256)
         x_out[r] = (flip && r < I1) ? -x[r] : x[r];
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double* dst, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = v;
+}
+
+// info[0] = Lanczos steps of the adjoint solve, info[1] = its final relative
+// Galerkin residual (NaN when it did not reach the tolerance).
+__global__ void adjoint_info_kernel(const SolveState* st, double* info) {
+    if (threadIdx.x == 0) {
+        info[0] = (double)st->lanczos;
+        info[1] = st->eig_unconverged ? NAN : st->ritz_res;
+    }
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(const double* src, int64_t n, double* dst) {
@@ -130,11 +144,15 @@ size_t hoscf_workspace_size(int op, const hoscf_tensor* T, const hoscf_options* 
             lay.build(*T, reinterpret_cast<void*>(0x1000), false, 1, nullptr, 0);
             return lay.used;
         case HOSCF_OP_SOLVE:
+        case HOSCF_OP_BACKWARD:
             lay.build(*T, nullptr, true, kDefaultKmax, nullptr, 0);
+            return lay.used;
+        case HOSCF_OP_TTVC_BACKWARD:
+            lay.build(*T, nullptr, false, 1, nullptr, 0);
             return lay.used;
         default: break;
     }
-    return hoscf_extra_workspace_size(op, T);
+    return 0;
 }
 
 int hoscf_ttvc(const hoscf_tensor* T, const double* x, void* blocks, double* g, double* scalars, void* ws,
@@ -317,6 +335,89 @@ int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* op
     if (info_host) *info_host = info;
     hipHostFree(h);
     return status;
+}
+
+int hoscf_backward(const hoscf_tensor* T, const double* x, double sigma, double g_sigma, const double* g_x,
+                   void* grad_T, int grad_dtype, double* mu_out, double* info, void* ws, size_t ws_bytes,
+                   void* stream) {
+    if (!valid_tensor(T) || !x || !grad_T) return HOSCF_INVALID_ARG;
+    if (grad_dtype != HOSCF_F32 && grad_dtype != HOSCF_F64) return HOSCF_INVALID_ARG;
+    if (!std::isfinite(sigma) || !std::isfinite(g_sigma)) return HOSCF_INVALID_ARG;
+    SolveLayout lay;
+    if (!ws || !lay.build(*T, nullptr, true, kDefaultKmax, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const BlockMap& map = lay.sweep.map;
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
+    HOSCF_TRY(hipGetLastError());
+    // blocks of M = (N-1) J at the unit factors (one read of T)
+    HOSCF_TRY(lay.sweep.run(x, lay.st, s));
+    double* mu = mu_out ? mu_out : lay.x;
+    if (g_x) {
+        HOSCF_TRY(lay.post.run(kPostAdjoint, lay.sweep.blocks, lay.sweep.blocksT, lay.sweep.xu, lay.g, lay.st, nullptr,
+                               0.0, 0.0, 1e-12, 1, s, g_x, mu, 0.0, sigma));
+    } else if (mu_out) {
+        const unsigned cgrid = (unsigned)std::min<int64_t>((map.D + 255) / 256, 1024);
+        hipLaunchKernelGGL(fill_kernel, dim3(cgrid), dim3(256), 0, s, mu_out, map.D, 0.0);
+        HOSCF_TRY(hipGetLastError());
+    }
+    if (info) {
+        hipLaunchKernelGGL(adjoint_info_kernel, dim3(1), dim3(64), 0, s, lay.st, info);
+        HOSCF_TRY(hipGetLastError());
+    }
+    OuterArgs oa{};
+    oa.out = grad_T;
+    oa.N = map.N;
+    for (int i = 0; i < map.N; ++i) oa.dims[i] = map.dims[i];
+    for (int i = 0; i <= map.N; ++i) oa.xoff[i] = map.xoff[i];
+    oa.x = lay.sweep.xu;
+    oa.v = g_x ? mu : lay.sweep.xu;
+    oa.c0 = g_sigma;
+    oa.cv = g_x ? -1.0 : 0.0;
+    oa.rows = 1;
+    for (int i = 0; i + 1 < map.N; ++i) oa.rows *= map.dims[i];
+    return outer_write(grad_dtype, oa, s);
+}
+
+int hoscf_ttvc_backward(const hoscf_tensor* T, const double* x, const void* blocks, const double* gbar,
+                        double sigma_bar, void* grad_T, int grad_dtype, double* grad_x, void* ws, size_t ws_bytes,
+                        void* stream) {
+    if (!valid_tensor(T) || !x) return HOSCF_INVALID_ARG;
+    if (grad_T && grad_dtype != HOSCF_F32 && grad_dtype != HOSCF_F64) return HOSCF_INVALID_ARG;
+    if (!std::isfinite(sigma_bar)) return HOSCF_INVALID_ARG;
+    SolveLayout lay;
+    if (!ws || !lay.build(*T, const_cast<void*>(blocks), false, 1, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const BlockMap& map = lay.sweep.map;
+    const unsigned cgrid = (unsigned)std::min<int64_t>((map.D + 255) / 256, 1024);
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
+    HOSCF_TRY(hipGetLastError());
+    if (grad_x) {
+        // blocks given: unit factors and transposed copies only; else one sweep
+        HOSCF_TRY(blocks ? lay.sweep.prepare(x, lay.st, s) : lay.sweep.run(x, lay.st, s));
+        const double* rhs = gbar;
+        if (!rhs) {
+            hipLaunchKernelGGL(fill_kernel, dim3(cgrid), dim3(256), 0, s, lay.x, map.D, 0.0);
+            HOSCF_TRY(hipGetLastError());
+            rhs = lay.x;
+        }
+        HOSCF_TRY(lay.post.run(kPostMatvec, lay.sweep.blocks, lay.sweep.blocksT, lay.sweep.xu, lay.g, lay.st, nullptr,
+                               0.0, 0.0, 0.0, 1, s, rhs, grad_x, sigma_bar, 0.0));
+    } else {
+        HOSCF_TRY(lay.sweep.prepare(x, lay.st, s));
+    }
+    if (!grad_T) return HOSCF_OK;
+    OuterArgs oa{};
+    oa.out = grad_T;
+    oa.N = map.N;
+    for (int i = 0; i < map.N; ++i) oa.dims[i] = map.dims[i];
+    for (int i = 0; i <= map.N; ++i) oa.xoff[i] = map.xoff[i];
+    oa.x = lay.sweep.xu;
+    oa.v = gbar ? gbar : lay.sweep.xu;
+    oa.c0 = sigma_bar;
+    oa.cv = gbar ? 1.0 : 0.0;
+    oa.rows = 1;
+    for (int i = 0; i + 1 < map.N; ++i) oa.rows *= map.dims[i];
+    return outer_write(grad_dtype, oa, s);
 }
 
 }  // extern "C"

@@ -1,0 +1,549 @@
+// Batched form: many small order-3 FP32 tensors, each solved by HOSCF
+// (Algorithm 1) with greedy rank-one deflation (the deflation of Section 5,
+// Example 3): for r = 1..R, HOSCF on T_b - sum_{s<r} sigma_s u_s1 o u_s2 o u_s3.
+//
+// One persistent launch.  A workgroup takes tensors from a queue (largest
+// first) and runs every rank-one term of a tensor to the end:
+//   * the three J blocks of the tensor live in LDS (at most 3 x 96 x 96
+//     FP32); the sweep streams T slab by slab (a slab T[i,:,:] is staged in
+//     LDS, the next one is in flight in registers) and accumulates in FP64;
+//   * deflation is implicit in block space: a previous term s adds
+//     -sigma_s (x_{s,k}'u_k) x_{s,m} x_{s,n}' to block (m, n) (k the third
+//     mode), so T is never rewritten;
+//   * the eigen-step is Lanczos with full reorthogonalisation on the LDS
+//     blocks; the Krylov basis lives in a per-workgroup slice of the
+//     workspace (L2-resident);
+//   * the stopping test, block normalisation and signs follow the single
+//     tensor path (same readings).
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "tridiag.h"
+
+namespace hoscf {
+
+constexpr int kBatchMaxDim = 96;
+constexpr int kBatchMaxD = 3 * kBatchMaxDim;
+constexpr int kBatchKmax = 64;  // Lanczos steps per eigen-step
+
+struct BatchItem {
+    const float* T;
+    int I[3];
+    int b;         // index in the caller's order
+    int D;
+    int64_t xoff;  // offset of x[b][0][0] in the packed factor arrays
+};
+
+struct BatchArgs {
+    const BatchItem* items;
+    int B, R;
+    double tol, eig_tol;
+    int max_iter, canonical;
+    const double* x0;
+    double* x_out;
+    double* sigma_out;
+    int32_t* status_out;
+    int32_t* iters_out;
+    double* scratch;     // [grid][(kBatchKmax + 1) * kBatchMaxD]
+    unsigned* counter;   // work queue head
+};
+
+// LDS layout (bytes): blocks A12 | A13 | A23 (FP32, sized for the largest
+// dims), the slab / eigen-step area, FP64 vectors and small scalars.
+constexpr int kBlkFloats = 3 * kBatchMaxDim * kBatchMaxDim;
+constexpr int kSlabFloats = kBatchMaxDim * kBatchMaxDim;
+struct BatchLds {
+    float blk[kBlkFloats];
+    union {
+        float slab[kSlabFloats];
+        double vec[kSlabFloats / 2];  // eigen-step: w, y and the staged Krylov vector
+    } a;
+    double u[kBatchMaxD];   // current unit factors (FP64)
+    double g[kBatchMaxD];   // mode vectors
+    float uf[kBatchMaxD];   // FP32 copy of u for the sweep
+    double al[kBatchKmax], be[kBatchKmax], b2[kBatchKmax], s[kBatchKmax];
+    double tri[4 * kBatchKmax];
+    double h[kBatchKmax + 8];
+    double red[16];
+    double defl[16 * 3];   // per previous term: sigma_s * (x_{s,k}' u_k) for the three blocks
+    double sc[8];
+    int item, stop;
+};
+
+template <int BT>
+__device__ double block_sum(double v, double* red) {
+    for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < BT / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// out = (N-1) J v = M v for the three blocks (rows split over threads);
+// v and out are FP64 vectors in LDS, in the stacked [u1; u2; u3] layout.
+__device__ void bmatvec(const BatchLds& L, const int* I, const double* v, double* out, int BT) {
+    const int I1 = I[0], I2 = I[1], I3 = I[2];
+    const float* A12 = L.blk;
+    const float* A13 = A12 + I1 * I2;
+    const float* A23 = A13 + I1 * I3;
+    const int D = I1 + I2 + I3;
+    for (int r = threadIdx.x; r < D; r += BT) {
+        double acc = 0.0;
+        if (r < I1) {
+            const int i = r;
+            for (int j = 0; j < I2; ++j) acc = fma((double)A12[i * I2 + j], v[I1 + j], acc);
+            for (int k = 0; k < I3; ++k) acc = fma((double)A13[i * I3 + k], v[I1 + I2 + k], acc);
+        } else if (r < I1 + I2) {
+            const int j = r - I1;
+            for (int i = 0; i < I1; ++i) acc = fma((double)A12[i * I2 + j], v[i], acc);
+            for (int k = 0; k < I3; ++k) acc = fma((double)A23[j * I3 + k], v[I1 + I2 + k], acc);
+        } else {
+            const int k = r - I1 - I2;
+            for (int i = 0; i < I1; ++i) acc = fma((double)A13[i * I3 + k], v[i], acc);
+            for (int j = 0; j < I2; ++j) acc = fma((double)A23[j * I3 + k], v[I1 + j], acc);
+        }
+        out[r] = acc;
+    }
+}
+
+template <int BT>
+__global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    BatchLds& L = *reinterpret_cast<BatchLds*>(lds_raw);
+    constexpr int QM = (kSlabFloats + BT - 1) / BT;  // slab elements per thread
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* V = a.scratch + (size_t)blockIdx.x * (kBatchKmax + 1) * kBatchMaxD;
+
+    for (;;) {
+        if (tid == 0) L.item = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int it = L.item;
+        __syncthreads();
+        if (it >= a.B) break;
+        const BatchItem item = a.items[it];
+        const int I[3] = {item.I[0], item.I[1], item.I[2]};
+        const int I1 = I[0], I2 = I[1], I3 = I[2];
+        const int D = item.D;
+        const int off[4] = {0, I1, I1 + I2, D};
+        const int n23 = I2 * I3;
+        float* A12 = L.blk;
+        float* A13 = A12 + I1 * I2;
+        float* A23 = A13 + I1 * I3;
+
+        for (int r = 0; r < a.R; ++r) {
+            const double* x0 = a.x0 + item.xoff + (int64_t)r * D;
+            double* xo = a.x_out + item.xoff + (int64_t)r * D;
+            // normalised start
+            for (int q = tid; q < D; q += BT) L.u[q] = x0[q];
+            __syncthreads();
+            int status = HOSCF_NOT_CONVERGED, iters = 0;
+            double sigma = 0.0;
+            for (int n = 0; n < 3; ++n) {
+                double s2 = 0.0;
+                for (int q = off[n] + tid; q < off[n + 1]; q += BT) s2 = fma(L.u[q], L.u[q], s2);
+                L.sc[n] = 0.0;
+                const double t = block_sum<BT>(s2, L.red);
+                if (tid == 0) L.sc[n] = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+                __syncthreads();
+            }
+            if (L.sc[0] == 0.0 || L.sc[1] == 0.0 || L.sc[2] == 0.0) status = HOSCF_DEGENERATE;
+            for (int q = tid; q < D; q += BT) {
+                const int n = q < I1 ? 0 : (q < I1 + I2 ? 1 : 2);
+                L.u[q] *= L.sc[n];
+            }
+            __syncthreads();
+
+            while (status == HOSCF_NOT_CONVERGED) {
+                // ---- deflation coefficients of the previous terms at u ----
+                // defl[3s + c]: c = 0 for block (1,2) (third mode 3), 1 for (1,3)
+                // (mode 2), 2 for (2,3) (mode 1): sigma_s * x_{s,k}' u_k
+                for (int s = 0; s < r; ++s) {
+                    const double* xs = a.x_out + item.xoff + (int64_t)s * D;
+                    const double sg = a.sigma_out[item.b * a.R + s];
+                    for (int c = 0; c < 3; ++c) {
+                        const int k = 2 - c;
+                        double d = 0.0;
+                        for (int q = off[k] + tid; q < off[k + 1]; q += BT) d = fma(xs[q], L.u[q], d);
+                        d = block_sum<BT>(d, L.red);
+                        if (tid == 0) L.defl[3 * s + c] = sg * d;
+                    }
+                }
+                for (int q = tid; q < D; q += BT) L.uf[q] = (float)L.u[q];
+                __syncthreads();
+
+                // ---- sweep: blocks at u, FP64 accumulation ----
+                double acc23[QM];
+                float cur[QM], nxt[QM];
+#pragma unroll
+                for (int q = 0; q < QM; ++q) {
+                    acc23[q] = 0.0;
+                    const int e = tid + q * BT;
+                    cur[q] = item.T[e < n23 ? e : 0];
+                }
+                double fro = 0.0;
+                for (int i = 0; i < I1; ++i) {
+#pragma unroll
+                    for (int q = 0; q < QM; ++q) {
+                        const int e = tid + q * BT;
+                        if (e < n23) L.a.slab[e] = cur[q];
+                    }
+                    const int inext = i + 1 < I1 ? i + 1 : i;
+                    const float* Tn = item.T + (int64_t)inext * n23;
+#pragma unroll
+                    for (int q = 0; q < QM; ++q) {
+                        const int e = tid + q * BT;
+                        nxt[q] = Tn[e < n23 ? e : 0];
+                    }
+                    __syncthreads();
+                    const double u1i = L.u[i];
+#pragma unroll
+                    for (int q = 0; q < QM; ++q) acc23[q] = fma((double)cur[q], u1i, acc23[q]);
+                    // row i of A12 (threads 0..I2-1) and of A13 (threads BT/2..BT/2+I3-1)
+                    if (tid < I2) {
+                        const int j = tid;
+                        double acc = 0.0;
+                        for (int k = 0; k < I3; ++k) acc = fma((double)L.a.slab[j * I3 + k], L.u[I1 + I2 + k], acc);
+                        double corr = 0.0;
+                        for (int s = 0; s < r; ++s) {
+                            const double* xs = a.x_out + item.xoff + (int64_t)s * D;
+                            corr = fma(L.defl[3 * s + 0] * xs[i], xs[I1 + j], corr);
+                        }
+                        const float v = (float)(acc - corr);
+                        A12[i * I2 + j] = v;
+                        fro = fma((double)v, (double)v, fro);
+                    } else if (tid >= BT / 2 && tid < BT / 2 + I3) {
+                        const int k = tid - BT / 2;
+                        double acc = 0.0;
+                        for (int j = 0; j < I2; ++j) acc = fma((double)L.a.slab[j * I3 + k], L.u[I1 + j], acc);
+                        double corr = 0.0;
+                        for (int s = 0; s < r; ++s) {
+                            const double* xs = a.x_out + item.xoff + (int64_t)s * D;
+                            corr = fma(L.defl[3 * s + 1] * xs[i], xs[I1 + I2 + k], corr);
+                        }
+                        const float v = (float)(acc - corr);
+                        A13[i * I3 + k] = v;
+                        fro = fma((double)v, (double)v, fro);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int q = 0; q < QM; ++q) cur[q] = nxt[q];
+                }
+#pragma unroll
+                for (int q = 0; q < QM; ++q) {
+                    const int e = tid + q * BT;
+                    if (e < n23) {
+                        const int j = e / I3, k = e - j * I3;
+                        double corr = 0.0;
+                        for (int s = 0; s < r; ++s) {
+                            const double* xs = a.x_out + item.xoff + (int64_t)s * D;
+                            corr = fma(L.defl[3 * s + 2] * xs[I1 + j], xs[I1 + I2 + k], corr);
+                        }
+                        const float v = (float)(acc23[q] - corr);
+                        A23[e] = v;
+                        fro = fma((double)v, (double)v, fro);
+                    }
+                }
+                fro = block_sum<BT>(fro, L.red);  // includes the barrier after the block writes
+
+                // ---- g = M u / 2, sigma, ||J||_F, residual ----
+                bmatvec(L, I, L.u, L.g, BT);
+                __syncthreads();
+                for (int q = tid; q < D; q += BT) L.g[q] *= 0.5;
+                __syncthreads();
+                double s0 = 0.0;
+                for (int q = tid; q < I1; q += BT) s0 = fma(L.u[q], L.g[q], s0);
+                sigma = block_sum<BT>(s0, L.red);
+                double rr = 0.0;
+                for (int q = tid; q < D; q += BT) {
+                    const double e = L.g[q] - sigma * L.u[q];
+                    rr = fma(e, e, rr);
+                }
+                rr = block_sum<BT>(rr, L.red);
+                const double normJ = sqrt(2.0 * fro) * 0.5;
+                const double den = normJ + fabs(sigma);
+                if (!isfinite(sigma) || !isfinite(normJ) || !isfinite(rr)) {
+                    status = HOSCF_NONFINITE;
+                    break;
+                }
+                if (!(den > 0.0)) {
+                    status = HOSCF_DEGENERATE;
+                    break;
+                }
+                const double res = sqrt(rr / 3.0) / den;
+                if (res <= a.tol) {
+                    status = HOSCF_OK;
+                    break;
+                }
+                if (iters >= a.max_iter) break;
+                ++iters;
+
+                // ---- eigen-step: Lanczos on J = M/2 from x~ = u/sqrt(3) ----
+                double* w = L.a.vec;                 // [D]
+                double* vj = L.a.vec + kBatchMaxD;   // staged V_j
+                const double is3 = 1.0 / sqrt(3.0);
+                for (int q = tid; q < D; q += BT) {
+                    V[q] = L.u[q] * is3;
+                    vj[q] = L.u[q] * is3;
+                }
+                __syncthreads();
+                int m = 0;
+                bool stop = false;
+                for (int j = 0; j < kBatchKmax && !stop; ++j) {
+                    bmatvec(L, I, vj, w, BT);
+                    __syncthreads();
+                    for (int q = tid; q < D; q += BT) w[q] *= 0.5;
+                    __syncthreads();
+                    // two passes of classical Gram-Schmidt against V_0..V_j
+                    for (int pass = 0; pass < 2; ++pass) {
+                        for (int i0 = wave; i0 <= j; i0 += BT / 64) {
+                            double d = 0.0;
+                            const double* Vi = V + (size_t)i0 * kBatchMaxD;
+                            for (int q = lane; q < D; q += 64) d = fma(Vi[q], w[q], d);
+                            for (int k = 32; k >= 1; k >>= 1) d += __shfl_xor(d, k);
+                            if (lane == 0) L.h[i0] = d;
+                        }
+                        __syncthreads();
+                        for (int q = tid; q < D; q += BT) {
+                            double t = 0.0;
+                            for (int i = 0; i <= j; ++i) t = fma(L.h[i], V[(size_t)i * kBatchMaxD + q], t);
+                            w[q] -= t;
+                        }
+                        if (tid == 0) L.al[j] = (pass == 0 ? 0.0 : L.al[j]) + L.h[j];
+                        __syncthreads();
+                    }
+                    double nn = 0.0;
+                    for (int q = tid; q < D; q += BT) nn = fma(w[q], w[q], nn);
+                    const double beta = sqrt(block_sum<BT>(nn, L.red));
+                    if (tid == 0) {
+                        L.be[j] = beta;
+                        L.b2[j] = beta * beta;
+                    }
+                    __syncthreads();
+                    m = j + 1;
+                    const bool invariant = beta <= 1e-14 * normJ;
+                    if (invariant || m == kBatchKmax || m <= 8 || (m % 4) == 0) {
+                        if (tid < 64) {
+                            double lmin = L.al[0], lmax = L.al[0];
+                            if (m > 1) extreme_eigs(L.al, L.b2, L.be, m, &lmin, &lmax);
+                            if (tid == 0) {
+                                const double th = (fabs(lmin) > fabs(lmax) * (1.0 + 1e-12)) ? lmin : lmax;
+                                for (int i = 0; i < m; ++i) L.s[i] = 1.0;
+                                const double zrep = 2.220446049250313e-16 * fmax(fabs(lmin), fabs(lmax)) + 1e-300;
+                                for (int rep = 0; rep < 3; ++rep) {
+                                    tri_solve(L.al, L.be, m, th, L.s, zrep, L.tri, L.tri + kBatchKmax,
+                                              L.tri + 2 * kBatchKmax, L.tri + 3 * kBatchKmax);
+                                    double nrm = 0.0;
+                                    for (int i = 0; i < m; ++i) nrm = fma(L.s[i], L.s[i], nrm);
+                                    nrm = sqrt(nrm);
+                                    for (int i = 0; i < m; ++i) L.s[i] /= nrm;
+                                }
+                                const double ritz = beta * fabs(L.s[m - 1]);
+                                L.stop = (ritz <= a.eig_tol * fmax(normJ, fabs(th))) || invariant || m == kBatchKmax;
+                            }
+                        }
+                        __syncthreads();
+                        stop = L.stop != 0;
+                        __syncthreads();
+                    }
+                    if (!stop) {
+                        const double ib = 1.0 / beta;
+                        double* Vn = V + (size_t)(j + 1) * kBatchMaxD;
+                        for (int q = tid; q < D; q += BT) {
+                            const double v = w[q] * ib;
+                            Vn[q] = v;
+                            vj[q] = v;
+                        }
+                        __syncthreads();
+                    }
+                }
+                // y = V_m s, block norms and largest-|entry| signs
+                double* y = w;
+                for (int q = tid; q < D; q += BT) {
+                    double t = 0.0;
+                    for (int i = 0; i < m; ++i) t = fma(L.s[i], V[(size_t)i * kBatchMaxD + q], t);
+                    y[q] = t;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    bool degenerate = false;
+                    double f0 = 1.0;
+                    for (int n = 0; n < 3; ++n) {
+                        double s2 = 0.0, bv = -1.0, bs = 0.0;
+                        for (int q = off[n]; q < off[n + 1]; ++q) {
+                            s2 = fma(y[q], y[q], s2);
+                            if (fabs(y[q]) > bv) {
+                                bv = fabs(y[q]);
+                                bs = y[q];
+                            }
+                        }
+                        if (!(s2 > 0.0)) degenerate = true;
+                        double f = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+                        if (a.canonical && n >= 1 && bs < 0.0) {
+                            f = -f;
+                            f0 = -f0;
+                        }
+                        L.sc[n] = f;
+                    }
+                    L.sc[0] *= f0;
+                    L.stop = degenerate ? 1 : 0;
+                }
+                __syncthreads();
+                if (L.stop) {
+                    status = HOSCF_DEGENERATE;
+                    break;
+                }
+                for (int q = tid; q < D; q += BT) {
+                    const int n = q < I1 ? 0 : (q < I1 + I2 ? 1 : 2);
+                    L.u[q] = y[q] * L.sc[n];
+                }
+                __syncthreads();
+            }
+            // final sign fix: sigma >= 0 via u_1
+            const bool flip = sigma < 0.0;
+            for (int q = tid; q < D; q += BT) xo[q] = (flip && q < I1) ? -L.u[q] : L.u[q];
+            if (tid == 0) {
+                a.sigma_out[item.b * a.R + r] = fabs(sigma);
+                a.status_out[item.b * a.R + r] = status;
+                if (a.iters_out) a.iters_out[item.b * a.R + r] = iters;
+            }
+            // the next term reads this term's factors and sigma
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void batch_reset_kernel(unsigned* counter) {
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+}  // namespace hoscf
+
+using namespace hoscf;
+
+struct hoscf_plan {
+    int B = 0, R = 0;
+    hoscf_options opts{};
+    BatchItem* items = nullptr;  // device, largest first
+    int grid = 0;
+    int bt = 256;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+constexpr size_t kLdsBytes = sizeof(BatchLds);
+
+template <int BT>
+int batch_grid() {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel<BT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&batch_kernel<BT>), BT,
+                                                     kLdsBytes) != hipSuccess)
+        return 0;
+    return cus * std::max(per, 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hoscf_batch_plan_create(int B, const hoscf_tensor* descs, int R, const hoscf_options* opts,
+                            hoscf_plan** out) {
+    if (!out) return HOSCF_INVALID_ARG;
+    *out = nullptr;
+    if (B < 0 || R < 1 || R > 16 || (B > 0 && !descs)) return HOSCF_INVALID_ARG;
+    hoscf_options o{};
+    o.algo = 0;
+    o.tol = 1e-6;
+    o.max_iter = 500;
+    o.canonical_sign = 1;
+    if (opts) o = *opts;
+    if (o.algo != 0 || !(o.tol >= 0.0) || o.max_iter < 0) return HOSCF_INVALID_ARG;
+    std::vector<BatchItem> items((size_t)B);
+    int64_t xoff = 0;
+    for (int b = 0; b < B; ++b) {
+        const hoscf_tensor& T = descs[b];
+        if (T.order != 3 || T.dtype != HOSCF_F32 || !T.data) return HOSCF_INVALID_ARG;
+        BatchItem& it = items[(size_t)b];
+        it.T = static_cast<const float*>(T.data);
+        for (int n = 0; n < 3; ++n) {
+            if (T.dims[n] < 1 || T.dims[n] > kBatchMaxDim) return HOSCF_INVALID_ARG;
+            it.I[n] = (int)T.dims[n];
+        }
+        it.b = b;
+        it.D = it.I[0] + it.I[1] + it.I[2];
+        it.xoff = xoff;
+        xoff += (int64_t)R * it.D;
+    }
+    // largest first: the queue then ends with the short items
+    std::stable_sort(items.begin(), items.end(), [](const BatchItem& p, const BatchItem& q) {
+        return (int64_t)p.I[0] * p.I[1] * p.I[2] > (int64_t)q.I[0] * q.I[1] * q.I[2];
+    });
+    hoscf_plan* p = new hoscf_plan();
+    p->B = B;
+    p->R = R;
+    p->opts = o;
+    p->bt = 256;
+    p->grid = batch_grid<256>();
+    if (p->grid <= 0) {
+        delete p;
+        return HOSCF_HIP_ERROR;
+    }
+    if (B > 0) {
+        if (hipMalloc(reinterpret_cast<void**>(&p->items), sizeof(BatchItem) * (size_t)B) != hipSuccess ||
+            hipMemcpy(p->items, items.data(), sizeof(BatchItem) * (size_t)B, hipMemcpyHostToDevice) != hipSuccess) {
+            if (p->items) (void)hipFree(p->items);
+            delete p;
+            return HOSCF_HIP_ERROR;
+        }
+    }
+    p->ws_bytes = 256 + (size_t)p->grid * (kBatchKmax + 1) * kBatchMaxD * sizeof(double);
+    *out = p;
+    return HOSCF_OK;
+}
+
+void hoscf_plan_destroy(hoscf_plan* plan) {
+    if (!plan) return;
+    if (plan->items) (void)hipFree(plan->items);
+    delete plan;
+}
+
+size_t hoscf_batch_workspace_size(const hoscf_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+int hoscf_solve_batched(const hoscf_plan* plan, const double* x0, double* x_out, double* sigma_out,
+                        int32_t* status_out, int32_t* iters_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan) return HOSCF_INVALID_ARG;
+    if (plan->B == 0) return HOSCF_OK;
+    if (!x0 || !x_out || !sigma_out || !status_out) return HOSCF_INVALID_ARG;
+    if (!ws || ws_bytes < plan->ws_bytes) return HOSCF_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchArgs a{};
+    a.items = plan->items;
+    a.B = plan->B;
+    a.R = plan->R;
+    a.tol = plan->opts.tol;
+    a.eig_tol = std::min(1e-8, std::max(1e-13, 1e-3 * plan->opts.tol));
+    a.max_iter = plan->opts.max_iter;
+    a.canonical = plan->opts.canonical_sign;
+    a.x0 = x0;
+    a.x_out = x_out;
+    a.sigma_out = sigma_out;
+    a.status_out = status_out;
+    a.iters_out = iters_out;
+    a.counter = static_cast<unsigned*>(ws);
+    a.scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + 256);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, a.counter);
+    hipLaunchKernelGGL(batch_kernel<256>, dim3((unsigned)plan->grid), dim3(256), kLdsBytes, s, a);
+    return hipGetLastError() == hipSuccess ? HOSCF_OK : HOSCF_HIP_ERROR;
+}
+
+}  // extern "C"

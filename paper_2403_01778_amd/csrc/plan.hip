@@ -139,6 +139,14 @@ bool SweepPlan::build(const hoscf_tensor& T, int fmt, const void* data, float sc
     return ar.ok;
 }
 
+hipError_t SweepPlan::prepare(const double* x, SolveState* st, hipStream_t s) const {
+    FactorOffsets off;
+    for (int i = 0; i <= map.N; ++i) off.off[i] = map.xoff[i];
+    hipError_t e = launch_prep(f64, x, map.N, off, xu, xa, st, s);
+    if (e != hipSuccess) return e;
+    return launch_transpose(f64, blocks, tr_, blocksT, s);
+}
+
 hipError_t SweepPlan::run(const double* x, SolveState* st, hipStream_t s, hipEvent_t* ev_k1) const {
     FactorOffsets off;
     for (int i = 0; i <= map.N; ++i) off.off[i] = map.xoff[i];

@@ -8,7 +8,13 @@ namespace hoscf {
 constexpr int kKmaxLds = 256;  // largest Lanczos dimension held in LDS
 constexpr int kVecLds = 8192;  // vectors up to this length are staged in LDS for the J products
 
-enum PostMode { kPostEpilogue = 0, kPostEigen = 1, kPostRqi = 2 };
+enum PostMode {
+    kPostEpilogue = 0,  // g, sigma, ||J||_F, residual only
+    kPostEigen = 1,     // + largest-magnitude eigenpair, new iterate
+    kPostRqi = 2,       // + Rayleigh step (Galerkin shifted solve from x~)
+    kPostAdjoint = 3,   // + projected shifted solve P(J - shift/(N-1) I)P mu = P rhs/(N-1)
+    kPostMatvec = 4     // + out = (N-1) J rhs + coef g
+};
 
 struct PostArgs {
     const void* blocks;
@@ -37,13 +43,17 @@ struct PostArgs {
     double* V;       // [(kmax+1) * D] Lanczos basis
     double* w;       // [D]
     double* red;     // [2][nwg][RK]
+    const double* rhs;  // [D] right-hand side (adjoint) or vector (matvec)
+    double* out;        // [D] mu (adjoint) or (N-1) J rhs + coef g (matvec)
+    double coef, shift;
 };
 
 class PostPlan {
    public:
     bool build(const BlockMap& map, bool f64_blocks, int kmax, int max_wg, Arena& ar);
     hipError_t run(int mode, const void* blocks, const void* blocksT, double* x, double* g, SolveState* st, double* scalars,
-                   double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s) const;
+                   double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s,
+                   const double* rhs = nullptr, double* out = nullptr, double coef = 0.0, double shift = 0.0) const;
     PostArgs a{};
     bool f64 = false;
 };

@@ -20,6 +20,7 @@
 
 #include "common.h"
 #include "post.h"
+#include "tridiag.h"
 
 namespace hoscf {
 
@@ -68,128 +69,6 @@ __device__ __forceinline__ void xred64(double* v, int lane, int& base) {
             xred64<1, STEPS - 1>(v, lane, base);
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Symmetric tridiagonal helpers (Lanczos matrix T_m: diag al, off-diag be).
-// ---------------------------------------------------------------------------
-
-// Number of eigenvalues of T_m smaller than x (Sturm sequence of the LDL'
-// pivots).
-__device__ int sturm_count(const double* al, const double* b2, int m, double x, double pivmin) {
-    int cnt = 0;
-    double d = al[0] - x;
-    if (fabs(d) < pivmin) d = -pivmin;
-    cnt += d < 0.0;
-    for (int k = 1; k < m; ++k) {
-        d = (al[k] - x) - b2[k - 1] / d;
-        if (fabs(d) < pivmin) d = -pivmin;
-        cnt += d < 0.0;
-    }
-    return cnt;
-}
-
-// Extreme eigenvalues of T_m by 32-way multisection per end (wave 0 only;
-// lanes 0-31 bracket the smallest, lanes 32-63 the largest).
-__device__ void extreme_eigs(const double* al, const double* b2, const double* be, int m, double* out_lo,
-                             double* out_hi) {
-    const int lane = threadIdx.x & 63;
-    double glo = 1e300, ghi = -1e300, bmax = 0.0;
-    for (int k = 0; k < m; ++k) {
-        const double r = (k > 0 ? fabs(be[k - 1]) : 0.0) + (k < m - 1 ? fabs(be[k]) : 0.0);
-        glo = fmin(glo, al[k] - r);
-        ghi = fmax(ghi, al[k] + r);
-        if (k < m - 1) bmax = fmax(bmax, b2[k]);
-    }
-    const double scale = fmax(fabs(glo), fabs(ghi));
-    const double pivmin = 1e-290 * fmax(1.0, bmax);
-    const double pad = 2.0 * 2.220446049250313e-16 * scale + pivmin;
-    double lo0 = glo - pad, hi0 = ghi + pad;  // interval for the smallest eigenvalue
-    double lo1 = glo - pad, hi1 = ghi + pad;  // interval for the largest
-    const bool low_half = lane < 32;
-    const int sub = lane & 31;
-    for (int round = 0; round < 14; ++round) {
-        const double lo = low_half ? lo0 : lo1, hi = low_half ? hi0 : hi1;
-        const double x = lo + (hi - lo) * (double)(sub + 1) / 33.0;
-        const int c = sturm_count(al, b2, m, x, pivmin);
-        // smallest: first point with count >= 1; largest: first point with count == m
-        const bool hit = low_half ? (c >= 1) : (c >= m);
-        const unsigned long long bal = __ballot(hit);
-        const unsigned lo_bits = (unsigned)(bal & 0xffffffffull);
-        const unsigned hi_bits = (unsigned)(bal >> 32);
-        // lane-uniform update of both intervals
-        const double xs_lo_step = (hi0 - lo0) / 33.0;
-        const double xs_hi_step = (hi1 - lo1) / 33.0;
-        if (lo_bits) {
-            const int f = __ffs(lo_bits) - 1;
-            const double nhi = lo0 + xs_lo_step * (f + 1);
-            const double nlo = f > 0 ? lo0 + xs_lo_step * f : lo0;
-            lo0 = nlo;
-            hi0 = nhi;
-        } else {
-            lo0 = lo0 + xs_lo_step * 32;
-        }
-        if (hi_bits) {
-            const int f = __ffs(hi_bits) - 1;
-            const double nhi = lo1 + xs_hi_step * (f + 1);
-            const double nlo = f > 0 ? lo1 + xs_hi_step * f : lo1;
-            lo1 = nlo;
-            hi1 = nhi;
-        } else {
-            lo1 = lo1 + xs_hi_step * 32;
-        }
-        const double tol = 4.0 * 2.220446049250313e-16 * scale + pivmin;
-        if (hi0 - lo0 <= tol && hi1 - lo1 <= tol) break;
-    }
-    *out_lo = 0.5 * (lo0 + hi0);
-    *out_hi = 0.5 * (lo1 + hi1);
-}
-
-// Solve (T_m - shift I) y = rhs by Gaussian elimination with partial
-// pivoting on the tridiagonal (single thread).  Zero pivots are replaced by
-// `zrep` when zrep > 0; otherwise the call reports singularity (returns false).
-__device__ bool tri_solve(const double* al, const double* be, int m, double shift, double* y, double zrep,
-                          double* d, double* du, double* du2, double* dl) {
-    for (int i = 0; i < m; ++i) {
-        d[i] = al[i] - shift;
-        if (i < m - 1) {
-            du[i] = be[i];
-            dl[i] = be[i];
-            du2[i] = 0.0;
-        }
-    }
-    for (int i = 0; i < m - 1; ++i) {
-        if (fabs(d[i]) >= fabs(dl[i])) {
-            if (d[i] == 0.0) {
-                if (zrep <= 0.0) return false;
-                d[i] = zrep;
-            }
-            const double f = dl[i] / d[i];
-            d[i + 1] -= f * du[i];
-            y[i + 1] -= f * y[i];
-        } else {
-            const double f = d[i] / dl[i];
-            d[i] = dl[i];
-            const double t = du[i];
-            du[i] = d[i + 1];
-            d[i + 1] = t - f * d[i + 1];
-            if (i < m - 2) {
-                du2[i] = du[i + 1];
-                du[i + 1] = -f * du[i + 1];
-            }
-            const double yt = y[i];
-            y[i] = y[i + 1];
-            y[i + 1] = yt - f * y[i + 1];
-        }
-    }
-    if (d[m - 1] == 0.0) {
-        if (zrep <= 0.0) return false;
-        d[m - 1] = zrep;
-    }
-    y[m - 1] /= d[m - 1];
-    if (m >= 2) y[m - 2] = (y[m - 2] - du[m - 2] * y[m - 1]) / d[m - 2];
-    for (int i = m - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / d[i];
-    return true;
 }
 
 // Data one workgroup writes and others read inside the launch (Krylov vectors,
@@ -493,6 +372,32 @@ __device__ void own_combine(const double* V, int64_t D, int m, int64_t r_lo, int
     }
 }
 
+// mine[n] = sum over own rows of block n of x[r] w[r]: the components of w
+// along the unit factors, removed by the projection onto the tangent space
+// {v : x_n' v_n = 0 for every n}.
+__device__ void own_xdots(const PostArgs& a, const double* w, int64_t r_lo, int64_t r_hi, double* mine, Lds& L) {
+    for (int n = 0; n < a.N; ++n) {
+        const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
+        const int64_t hi = r_hi < L.xoff[n + 1] ? r_hi : L.xoff[n + 1];
+        double s = 0.0;
+        for (int64_t r = lo + threadIdx.x; r < hi; r += BS) s = fma(a.x[r], w[r], s);
+        s = wg_sum(s, L.red4);
+        if (threadIdx.x == 0) mine[n] = s;
+    }
+}
+
+// w[r] -= c[n] x[r] over own rows of block n (c summed over the grid).
+__device__ void own_xsub(const PostArgs& a, double* w, const double* c, int64_t r_lo, int64_t r_hi, const Lds& L) {
+    __syncthreads();
+    for (int n = 0; n < a.N; ++n) {
+        const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
+        const int64_t hi = r_hi < L.xoff[n + 1] ? r_hi : L.xoff[n + 1];
+        const double cn = c[n];
+        for (int64_t r = lo + threadIdx.x; r < hi; r += BS) w[r] = fma(-cn, a.x[r], w[r]);
+    }
+    __syncthreads();
+}
+
 template <typename B>
 __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     __shared__ Lds L;
@@ -554,6 +459,14 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         }
     }
     bool done = a.mode == kPostEpilogue || nonfinite || zero || (a.mode == kPostEigen && res <= a.tol);
+    if (a.mode == kPostMatvec) {
+        // out = (N-1) J rhs + coef g over own rows (g of this workgroup's rows)
+        matvec_rows<B, false>(a, a.rhs, a.out, 1.0, false, r_lo, r_hi, vlds);
+        __syncthreads();
+        for (int64_t r = r_lo + tid; r < r_hi; r += BS) a.out[r] = fma(a.coef, a.g[r], a.out[r]);
+        done = true;
+    }
+    const bool proj = a.mode == kPostAdjoint;
 
     // ---- B. Lanczos from x~ --------------------------------------------------
     const int kmax = a.kmax;
@@ -561,24 +474,53 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     double* w = a.w;
     int m = 0;
     double rho = 0.0;
-    if (!done) {
-        for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
-            st_ag(V + r, a.x[r] * inv_sqrtN);
-            w[r] = a.g[r] * inv_sqrtN;  // J x~ = [g_n] / sqrt(N)
+    double rb = 0.0;  // adjoint: ||P rhs|| / (N-1), the scale of the Galerkin solution
+    if (!done && proj) {
+        // V_0 = P rhs / ||P rhs||, with ||P rhs||^2 = ||rhs||^2 - sum_n (x_n' rhs_n)^2
+        own_xdots(a, a.rhs, r_lo, r_hi, L.mine, L);
+        double rr2 = 0.0;
+        for (int64_t r = r_lo + tid; r < r_hi; r += BS) rr2 = fma(a.rhs[r], a.rhs[r], rr2);
+        wg_to_mine(rr2, a.N, L);
+        allreduce(a, a.N + 1, parity, L, vlds);
+        double nb2 = L.hsum[a.N];
+        for (int n = 0; n < a.N; ++n) nb2 -= L.hsum[n] * L.hsum[n];
+        if (!(nb2 > 0.0)) {
+            // no tangent component: the solution is zero
+            for (int64_t r = r_lo + tid; r < r_hi; r += BS) a.out[r] = 0.0;
+            done = true;
+        } else {
+            const double ib = 1.0 / sqrt(nb2);
+            rb = sqrt(nb2) * inv_n1;
+            for (int n = 0; n < a.N; ++n) {
+                const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
+                const int64_t hi = r_hi < L.xoff[n + 1] ? r_hi : L.xoff[n + 1];
+                const double cn = L.hsum[n];
+                for (int64_t r = lo + tid; r < hi; r += BS) st_ag(V + r, fma(-cn, a.x[r], a.rhs[r]) * ib);
+            }
         }
+    }
+    if (!done) {
+        if (!proj)
+            for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
+                st_ag(V + r, a.x[r] * inv_sqrtN);
+                w[r] = a.g[r] * inv_sqrtN;  // J x~ = [g_n] / sqrt(N)
+            }
         grid_barrier(a.bar, a.nwg, &L.timeout);  // V_0 complete before any matvec reads it
+        const int NP = proj ? a.N : 0;           // projection components per reduction
         bool stop = false;
         for (int j = 0; j < kmax && !stop; ++j) {
-            if (j > 0) {
+            if (j > 0 || proj) {
                 matvec_rows<B, true>(a, V + (size_t)j * D, w, inv_n1, false, r_lo, r_hi, vlds);
                 __syncthreads();
                 if (j == 1) HOSCF_MARK(5);
             }
             // pass 1: h_i = V_i . w over own rows
             own_dots(V, w, D, j, r_lo, r_hi, L.mine);
-            allreduce(a, j + 1, parity, L, vlds);
+            if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 1, L);
+            allreduce(a, j + 1 + NP, parity, L, vlds);
             if (j == 1) HOSCF_MARK(10);
             own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+            if (proj) own_xsub(a, w, L.hsum + j + 1, r_lo, r_hi, L);
             if (j == 1) HOSCF_MARK(11);
             if (tid == 0) L.al[j] = L.hsum[j];
             __syncthreads();
@@ -588,12 +530,15 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
             nn = wg_sum(nn, L.red4);
             if (tid == 0) L.mine[j + 1] = nn;
-            allreduce(a, j + 2, parity, L, vlds);
+            if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 2, L);
+            allreduce(a, j + 2 + NP, parity, L, vlds);
             if (j == 1) HOSCF_MARK(12);
             double corr2 = 0.0;
             for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
+            for (int i = 0; i < NP; ++i) corr2 = fma(L.hsum[j + 2 + i], L.hsum[j + 2 + i], corr2);
             const double beta = sqrt(fmax(L.hsum[j + 1] - corr2, 0.0));
             own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+            if (proj) own_xsub(a, w, L.hsum + j + 2, r_lo, r_hi, L);
             if (tid == 0) {
                 L.al[j] += L.hsum[j];
                 L.be[j] = beta;
@@ -601,7 +546,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             }
             __syncthreads();
             m = j + 1;
-            rho = L.al[0];
+            rho = proj ? a.shift * inv_n1 : L.al[0];
             const bool invariant = beta <= 1e-14 * normJ;
             const bool check = invariant || m == kmax || m <= 8 || (m % 4) == 0;
             if (check) {
@@ -663,6 +608,18 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             if (j == 1) HOSCF_MARK(6);
         }
         HOSCF_MARK(7);
+    }
+
+    if (!done && proj) {
+        // mu = rb V_m t, t solving (T_m - shift/(N-1)) t = e_1
+        own_combine(V, D, m, r_lo, r_hi, L.s, L.part, w, false);
+        for (int64_t r = r_lo + tid; r < r_hi; r += BS) a.out[r] = (L.ok ? rb : 0.0) * w[r];
+        if (blockIdx.x == 0 && tid == 0) {
+            a.st->lanczos = m;
+            a.st->ritz_res = L.ritz;
+            a.st->eig_unconverged = (!L.ok || L.ritz > a.solve_tol) ? 1 : 0;
+        }
+        done = true;
     }
 
     // ---- C. the new iterate ---------------------------------------------------
@@ -855,8 +812,13 @@ bool PostPlan::build(const BlockMap& map, bool f64_blocks, int kmax, int max_wg,
 }
 
 hipError_t PostPlan::run(int mode, const void* blocks, const void* blocksT, double* x, double* g, SolveState* st, double* scalars,
-                         double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s) const {
+                         double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s,
+                         const double* rhs, double* out, double coef, double shift) const {
     PostArgs args = a;
+    args.rhs = rhs;
+    args.out = out;
+    args.coef = coef;
+    args.shift = shift;
     args.mode = mode;
     args.blocks = blocks;
     args.blocksT = const_cast<void*>(blocksT);

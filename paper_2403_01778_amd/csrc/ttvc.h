@@ -94,6 +94,9 @@ class SweepPlan {
                const SweepTuning& tune);
     // ev_k1 (optional): two events per K1 node, recorded around each launch.
     hipError_t run(const double* x, SolveState* st, hipStream_t s, hipEvent_t* ev_k1 = nullptr) const;
+    // Only the factor preparation (unit factors in xu) and the transposed
+    // block copies, for blocks already in `blocks` (no read of T).
+    hipError_t prepare(const double* x, SolveState* st, hipStream_t s) const;
     int num_nodes() const { return (int)nodes_.size(); }
 
     BlockMap map;

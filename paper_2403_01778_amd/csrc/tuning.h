@@ -14,5 +14,3 @@ SweepTuning tuning_from(const int64_t* tiling);
 SweepTuning lookup_tuning(const hoscf_tensor& T);
 
 }  // namespace hoscf
-
-extern "C" size_t hoscf_extra_workspace_size(int op, const hoscf_tensor* T);

@@ -59,7 +59,7 @@ _lib.hoscf_quantize.restype = ctypes.c_int
 _lib.hoscf_backward.argtypes = [ctypes.POINTER(HoscfTensor), _P, ctypes.c_double, ctypes.c_double, _P, _P,
                                 ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]
 _lib.hoscf_backward.restype = ctypes.c_int
-_lib.hoscf_ttvc_backward.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, _P, ctypes.c_double, _P,
+_lib.hoscf_ttvc_backward.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, ctypes.c_double, _P,
                                      ctypes.c_int, _P, _P, ctypes.c_size_t, _P]
 _lib.hoscf_ttvc_backward.restype = ctypes.c_int
 _lib.hoscf_profile_sweep.argtypes = [ctypes.POINTER(HoscfTensor), _P, _P, _P, ctypes.c_int,
@@ -294,3 +294,129 @@ def split(x: torch.Tensor, dims: Sequence[int]) -> List[torch.Tensor]:
         out.append(x[off:off + d])
         off += d
     return out
+
+
+_GRAD_DT = {torch.float32: F32, torch.float64: F64}
+
+
+def backward(T: torch.Tensor, x: torch.Tensor, sigma: float, g_sigma: float, g_x: Optional[torch.Tensor] = None,
+             grad_dtype: torch.dtype = torch.float32, scale: float = 1.0, return_info: bool = False):
+    """Gradient of L(sigma, u) w.r.t. T at a converged solve (hoscf_backward):
+    returns (grad_T, mu) or (grad_T, mu, (lanczos_steps, rel_residual))."""
+    desc = describe(T, scale)
+    D = sum(T.shape)
+    x = x.to(device=T.device, dtype=torch.float64).contiguous()
+    gx = None if g_x is None else g_x.to(device=T.device, dtype=torch.float64).contiguous()
+    grad = torch.empty(T.shape, dtype=grad_dtype, device=T.device)
+    mu = torch.empty(D, dtype=torch.float64, device=T.device)
+    info = torch.empty(2, dtype=torch.float64, device=T.device)
+    ws = _workspace(workspace_size(OP_BACKWARD, desc), T.device)
+    _check(_lib.hoscf_backward(ctypes.byref(desc), x.data_ptr(), float(sigma), float(g_sigma), _ptr(gx),
+                               grad.data_ptr(), _GRAD_DT[grad_dtype], mu.data_ptr(), info.data_ptr(), ws.data_ptr(),
+                               ws.numel(), _stream()), "hoscf_backward")
+    if return_info:
+        i = info.cpu()
+        return grad, mu, (int(i[0]), float(i[1]))
+    return grad, mu
+
+
+def ttvc_backward(T: torch.Tensor, x: torch.Tensor, gbar: Optional[torch.Tensor], sigma_bar: float,
+                  blocks_flat: Optional[torch.Tensor] = None, want_grad_T: bool = True,
+                  grad_dtype: torch.dtype = torch.float32, scale: float = 1.0):
+    """Adjoint of ttvc's (g, sigma) (hoscf_ttvc_backward): (grad_T or None,
+    grad_x) where grad_x is w.r.t. the unit factors."""
+    desc = describe(T, scale)
+    D = sum(T.shape)
+    x = x.to(device=T.device, dtype=torch.float64).contiguous()
+    gb = None if gbar is None else gbar.to(device=T.device, dtype=torch.float64).contiguous()
+    grad = torch.empty(T.shape, dtype=grad_dtype, device=T.device) if want_grad_T else None
+    gx = torch.empty(D, dtype=torch.float64, device=T.device)
+    ws = _workspace(workspace_size(OP_TTVC_BACKWARD, desc), T.device)
+    _check(_lib.hoscf_ttvc_backward(ctypes.byref(desc), x.data_ptr(), _ptr(blocks_flat), _ptr(gb), float(sigma_bar),
+                                    _ptr(grad), _GRAD_DT[grad_dtype], gx.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream()), "hoscf_ttvc_backward")
+    return grad, gx
+
+
+class _SolveFn(torch.autograd.Function):
+    """(sigma, x) = HOSCF solve of T from x0; differentiable w.r.t. T through
+    the stationarity conditions (hoscf_backward).  x0 gets no gradient."""
+
+    @staticmethod
+    def forward(ctx, T, x0, opts):
+        sig, x, info = solve_raw(T.detach().contiguous(), x0.detach(), opts)
+        ctx.save_for_backward(T, x)
+        ctx.sigma = sig
+        return torch.tensor(sig, dtype=torch.float64, device=T.device), x
+
+    @staticmethod
+    def backward(ctx, g_sigma, g_x):
+        T, x = ctx.saved_tensors
+        gs = 0.0 if g_sigma is None else float(g_sigma)
+        gdt = T.dtype if T.dtype in (torch.float32, torch.float64) else torch.float32
+        grad, _ = backward(T.detach(), x, ctx.sigma, gs, g_x, grad_dtype=gdt)
+        return grad.to(T.dtype), None, None
+
+
+def solve(T: torch.Tensor, x0: torch.Tensor, **opts) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Differentiable HOSCF / iHOSCF solve: returns (sigma, x) as FP64 device
+    tensors; gradients flow to T (FP32 or FP64 storage)."""
+    return _SolveFn.apply(T, x0, options(**opts))
+
+
+class BatchPlan:
+    """Plan for the batched form (hoscf_batch_plan_create): B order-3 FP32
+    device tensors (dims <= 96), R rank-one terms each by greedy deflation.
+    Keeps the tensors alive; frees the plan on deletion."""
+
+    def __init__(self, tensors: Sequence[torch.Tensor], R: int, tol: float = 1e-6, max_iter: int = 500,
+                 canonical_sign: bool = True):
+        self.tensors = [t.contiguous() for t in tensors]
+        self.R = int(R)
+        self.dims = [tuple(int(d) for d in t.shape) for t in self.tensors]
+        self.D = [sum(d) for d in self.dims]
+        self.offsets = []
+        off = 0
+        for D in self.D:
+            self.offsets.append(off)
+            off += self.R * D
+        self.total = off
+        descs = (HoscfTensor * max(1, len(self.tensors)))()
+        for i, t in enumerate(self.tensors):
+            descs[i] = describe(t)
+        opts = options(algo="hoscf", tol=tol, max_iter=max_iter, canonical_sign=canonical_sign)
+        h = ctypes.c_void_p()
+        _check(_lib.hoscf_batch_plan_create(len(self.tensors), descs, self.R, ctypes.byref(opts), ctypes.byref(h)),
+               "hoscf_batch_plan_create")
+        self._h = h
+        self.device = self.tensors[0].device if self.tensors else torch.device("cuda")
+        self.ws = _workspace(_lib.hoscf_batch_workspace_size(h), self.device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.hoscf_plan_destroy(h)
+            self._h = None
+
+    def outputs(self):
+        """Preallocated (x_out, sigma, status, iters) for run(); reuse them
+        under graph capture."""
+        dev = self.device
+        B = len(self.tensors)
+        return (torch.empty(self.total, dtype=torch.float64, device=dev),
+                torch.empty(B * self.R, dtype=torch.float64, device=dev),
+                torch.empty(B * self.R, dtype=torch.int32, device=dev),
+                torch.empty(B * self.R, dtype=torch.int32, device=dev))
+
+    def run(self, x0: torch.Tensor, out=None):
+        """One persistent launch on the current stream (no allocation and no
+        synchronisation when `out` is given)."""
+        x_out, sig, st, it = out if out is not None else self.outputs()
+        _check(_lib.hoscf_solve_batched(self._h, x0.data_ptr(), x_out.data_ptr(), sig.data_ptr(), st.data_ptr(),
+                                        it.data_ptr(), self.ws.data_ptr(), self.ws.numel(), _stream()),
+               "hoscf_solve_batched")
+        return x_out, sig, st, it
+
+    def factors(self, x_out: torch.Tensor, b: int, r: int) -> torch.Tensor:
+        o = self.offsets[b] + r * self.D[b]
+        return x_out[o:o + self.D[b]]

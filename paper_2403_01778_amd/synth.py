@@ -98,6 +98,16 @@ def planted_rank_one(dims: Sequence[int], lam: float, seed: int, dtype=np.float3
     return T, fac
 
 
+def planted_cp(dims: Sequence[int], lams: Sequence[float], seed: int, dtype=np.float32,
+               noise_std: float = 1.0) -> Tuple[np.ndarray, List[List[np.ndarray]]]:
+    """N(0,1) noise + sum_r lams[r] * a_r1 o ... o a_rN with unit Gaussian
+    planted factors (drawn term by term, mode by mode)."""
+    rng = _rng(seed, 1)
+    fac = [[unit_gaussian(rng, d) for d in dims] for _ in lams]
+    T = gaussian_plus_cp(dims, list(lams), fac, seed, noise_std=noise_std, dtype=dtype)
+    return T, fac
+
+
 def planted_lambda(dims: Sequence[int], factor: float = 3.0) -> float:
     """factor * E||noise||_F / sqrt(max dim) with E||noise||_F read as
     sqrt(prod dims)."""

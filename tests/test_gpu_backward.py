@@ -1,0 +1,161 @@
+"""GPU parity of the backward passes (hoscf_backward, hoscf_ttvc_backward)
+against the FP64 oracle's dense bordered solve and adjoint formulas, plus an
+end-to-end finite-difference check through the GPU solve itself.
+
+Bars: FP64 storage, mu and dL/dT within 1e-9 of the oracle (relative to the
+largest entry; the projected solve stops at a 1e-12 relative residual and the
+system's conditioning at these points is below 1e3); FP32 storage and FP32
+gradients within 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2403_01778_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _kkt_point(lib, T, seed, tol=1e-13):
+    x0 = synth.init_factors(T.shape, seed)
+    sig, x, info = lib.solve_raw(torch.from_numpy(T).to(DEV), torch.from_numpy(x0),
+                                 lib.options(algo="hoscf", tol=tol, max_iter=2000))
+    assert info.status == 0, info
+    return sig, x
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("dims", [(12, 10, 9), (7, 6, 5, 4), (9, 8, 7, 6, 5), (30, 40)])
+def test_backward_matches_oracle_fp64(lib, dims):
+    print(f"[bwd] dims={dims}", flush=True)
+    T, _ = synth.planted_rank_one(dims, synth.planted_lambda(dims), 50 + len(dims), dtype=np.float64)
+    sig, x = _kkt_point(lib, T, 50)
+    rng = np.random.default_rng(9)
+    g_sigma = float(rng.standard_normal())
+    g_x = rng.standard_normal(sum(dims))
+    grad, mu, (steps, rres) = lib.backward(torch.from_numpy(T).to(DEV), x, sig, g_sigma, torch.from_numpy(g_x),
+                                           grad_dtype=torch.float64, return_info=True)
+    xs = oracle.split(x.cpu().numpy(), dims)
+    dT_ref, mu_ref = oracle.grad_solve(T, xs, sig, g_sigma, oracle.split(g_x, dims))
+    print(f"  lanczos={steps} res={rres:.2e}", flush=True)
+    assert np.isfinite(rres) and rres <= 1e-12
+    mu_np = mu.cpu().numpy()
+    assert _rel(mu_np, oracle.stack(mu_ref)) <= 1e-9
+    for n, m in enumerate(oracle.split(mu_np, dims)):  # tangent
+        assert abs(float(xs[n] @ m)) <= 1e-12 * max(1.0, float(np.abs(mu_np).max()))
+    assert _rel(grad.cpu().numpy(), dT_ref) <= 1e-9
+
+
+def test_backward_envelope_only(lib):
+    """g_x = 0: dL/dT = g_sigma u_1 o u_2 o u_3 exactly (envelope theorem)."""
+    dims = (11, 13, 7)
+    T, _ = synth.planted_rank_one(dims, 20.0, 3, dtype=np.float64)
+    sig, x = _kkt_point(lib, T, 3)
+    grad, mu = lib.backward(torch.from_numpy(T).to(DEV), x, sig, 2.5, None, grad_dtype=torch.float64)
+    xs = oracle.split(x.cpu().numpy(), dims)
+    xs = [v / np.linalg.norm(v) for v in xs]
+    assert _rel(grad.cpu().numpy(), 2.5 * oracle.outer(xs)) <= 1e-14
+    assert float(mu.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dims", [(40, 30, 20), (10, 12, 14, 8)])
+def test_backward_fp32(lib, dims):
+    T, _ = synth.large_planted(dims, seed=70 + len(dims))
+    sig, x = _kkt_point(lib, T, 70, tol=1e-6)
+    rng = np.random.default_rng(10)
+    g_x = rng.standard_normal(sum(dims))
+    grad, mu = lib.backward(torch.from_numpy(T).to(DEV), x, sig, 1.0, torch.from_numpy(g_x),
+                            grad_dtype=torch.float32)
+    xs = oracle.split(x.cpu().numpy(), dims)
+    dT_ref, mu_ref = oracle.grad_solve(T.astype(np.float64), xs, sig, 1.0, oracle.split(g_x, dims))
+    assert _rel(mu.cpu().numpy(), oracle.stack(mu_ref)) <= 1e-5
+    assert _rel(grad.double().cpu().numpy(), dT_ref) <= 1e-5
+
+
+def test_backward_finite_difference_through_gpu_solve(lib):
+    """<dL/dT, E> against central differences of L = sigma + w'x where every
+    evaluation of L is a GPU solve (FP64, restarted from the converged point)."""
+    dims = (9, 8, 7)
+    T, _ = synth.planted_rank_one(dims, 15.0, 21, dtype=np.float64)
+    sig, x = _kkt_point(lib, T, 21)
+    rng = np.random.default_rng(22)
+    w = rng.standard_normal(sum(dims))
+    E = rng.standard_normal(dims)
+    grad, _ = lib.backward(torch.from_numpy(T).to(DEV), x, sig, 1.0, torch.from_numpy(w),
+                           grad_dtype=torch.float64)
+    x_star = x.cpu().numpy()
+
+    def loss(Tp):
+        s, xp, info = lib.solve_raw(torch.from_numpy(np.ascontiguousarray(Tp)).to(DEV), torch.from_numpy(x_star),
+                                    lib.options(algo="hoscf", tol=1e-14, max_iter=500, stall_iters=20))
+        xp = xp.cpu().numpy()
+        return s + float(w @ xp)
+
+    fd = oracle.fd_directional(loss, T, E, h=1e-6)
+    an = float(np.sum(grad.cpu().numpy() * E))
+    assert an == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+@pytest.mark.parametrize("dims", [(9, 8, 7), (6, 5, 4, 7), (20, 16)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("given_blocks", [True, False])
+def test_ttvc_backward_matches_oracle(lib, dims, dtype, given_blocks):
+    rng = np.random.default_rng(sum(dims))
+    T = rng.standard_normal(dims)
+    Tt = torch.from_numpy(T).to(dtype).to(DEV)
+    Tnp = Tt.double().cpu().numpy()
+    x = synth.init_factors(dims, 5)
+    xs = oracle.normalize_blocks(x, dims)
+    gbar = rng.standard_normal(sum(dims))
+    sbar = 0.7
+    blocks = lib.ttvc(Tt, torch.from_numpy(x)).blocks_flat if given_blocks else None
+    gT, gx = lib.ttvc_backward(Tt, torch.from_numpy(x), torch.from_numpy(gbar), sbar, blocks_flat=blocks,
+                               grad_dtype=torch.float64)
+    dT_ref, dx_ref = oracle.grad_ttvc(Tnp, xs, oracle.split(gbar, dims), sbar)
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    assert _rel(gT.cpu().numpy(), dT_ref) <= 1e-14
+    assert _rel(gx.cpu().numpy(), oracle.stack(dx_ref)) <= tol
+
+
+def test_autograd_solve(lib):
+    """torch.autograd through hoscf.solve: T.grad equals the oracle's dL/dT."""
+    dims = (10, 9, 8)
+    T, _ = synth.planted_rank_one(dims, 12.0, 31, dtype=np.float64)
+    x0 = synth.init_factors(dims, 31)
+    w = np.random.default_rng(32).standard_normal(sum(dims))
+    Tt = torch.from_numpy(T).to(DEV).requires_grad_(True)
+    sig, x = lib.solve(Tt, torch.from_numpy(x0), algo="hoscf", tol=1e-13, max_iter=2000)
+    L = sig + (x * torch.from_numpy(w).to(DEV)).sum()
+    L.backward()
+    xs = oracle.split(x.detach().cpu().numpy(), dims)
+    dT_ref, _ = oracle.grad_solve(T, xs, float(sig), 1.0, oracle.split(w, dims))
+    assert _rel(Tt.grad.cpu().numpy(), dT_ref) <= 1e-9
+
+
+def test_backward_c5_item_full_size(lib):
+    """One item of the 64 x 256^3 workload (planted rank-2, lambdas 768 and
+    512): the projected solve against the oracle's dense bordered solve
+    (D = 768), dL/dT on sampled entries against mu and u."""
+    dims = (256, 256, 256)
+    T, _ = synth.planted_cp(dims, [768.0, 512.0], 6)
+    rng = np.random.default_rng(6)
+    sig, x = _kkt_point(lib, T, 1006, tol=1e-6)
+    w = np.random.default_rng(7).standard_normal(768)
+    grad, mu = lib.backward(torch.from_numpy(T).to(DEV), x, sig, 1.0, torch.from_numpy(w))
+    xs = oracle.split(x.cpu().numpy(), dims)
+    _, mu_ref = oracle.grad_solve(T.astype(np.float64), xs, sig, 1.0, oracle.split(w, dims))
+    mu_np = mu.cpu().numpy()
+    assert _rel(mu_np, oracle.stack(mu_ref)) <= 1e-5
+    us = [v / np.linalg.norm(v) for v in xs]
+    ms = oracle.split(mu_np, dims)
+    g = grad.cpu().numpy()
+    idx = rng.integers(0, 256, size=(2000, 3))
+    for i, j, k in idx:
+        want = us[0][i] * us[1][j] * us[2][k] - (ms[0][i] * us[1][j] * us[2][k] + us[0][i] * ms[1][j] * us[2][k]
+                                                 + us[0][i] * us[1][j] * ms[2][k])
+        assert abs(g[i, j, k] - want) <= 1e-6 * (abs(want) + 1e-3)
