@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the precision, batched and backward legs")
     ap.add_argument("--profile-reps", type=int, default=20)
     return ap.parse_args()
 
@@ -82,6 +83,124 @@ def cpu_baseline(T, x0):
     return {"value": round(iters * T.nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{iters} oracle HOSCF iterations (FP64 sweep + dense eigh) on the 800^3 FP32 workload, "
                       f"{dt:.1f} s; {cores} BLAS threads"}
+
+
+def _timed(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def leg_precision(hoscf, synth, reps=2):
+    """Order-5 64^5 rank-5 CP + 1% noise: plain FP32 HOSCF against the
+    two-phase precision form (BF16 / FP8-E4M3 sweeps, then FP32 refinement),
+    sigma error against the FP64 oracle's T(u) on the FP32 tensor, and the
+    level-1 TTVc bandwidth per storage format."""
+    import numpy as np
+    import torch
+
+    import oracle
+    dims = (64,) * 5
+    T32, _, _ = synth.cp_plus_noise(dims, 5, 0.01, seed=4)
+    x0 = torch.from_numpy(synth.init_factors(dims, 1004))
+    Td = torch.from_numpy(T32).cuda()
+    out = {"workload": "order-5 64^5 rank-5 N(0,1) CP + 1% noise, seed 4, tol 1e-6, tol_lp 1e-3"}
+    opts = hoscf.options(algo="hoscf", tol=1e-6, max_iter=300, tol_lp=1e-3)
+    hoscf.solve_raw(Td, x0, opts)
+    dt, (sig32, x32, inf32) = _timed(lambda: hoscf.solve_raw(Td, x0, opts), reps)
+    xs = oracle.split(x32.cpu().numpy(), dims)
+    s_ref = oracle.objective(T32, xs)
+    r = hoscf.profile_sweep(Td, x32, reps=5)
+    out["f32"] = {"solves_per_s": round(1 / dt, 3), "sweeps": inf32.sweeps, "status": inf32.status,
+                  "sigma": sig32, "sigma_rel_err_vs_oracle": abs(sig32 - s_ref) / abs(s_ref),
+                  "ttvc_GBps": round(r[3] / r[2] / 1e6, 1)}
+    for fmt in ("bf16", "fp8"):
+        Tq, sc = hoscf.quantize(Td, fmt)
+        scale = float(sc.item())
+        run = lambda: hoscf.solve_raw(Tq, x0, opts, scale=scale, data_f32=Td)  # noqa: E731
+        run()
+        dt_q, (sig, x, inf) = _timed(run, reps)
+        xs = oracle.split(x.cpu().numpy(), dims)
+        s_o = oracle.objective(T32, xs)
+        ang = max(oracle.angle(a, b) for a, b in zip(xs, oracle.split(x32.cpu().numpy(), dims)))
+        rq = hoscf.profile_sweep(Tq, x, reps=5, scale=scale)
+        out[fmt] = {"solves_per_s": round(1 / dt_q, 3), "speedup_vs_f32": round(dt / dt_q, 3),
+                    "sweeps": inf.sweeps, "lp_sweeps": inf.lp_sweeps, "status": inf.status, "sigma": sig,
+                    "sigma_rel_err_vs_oracle": abs(sig - s_o) / abs(s_o),
+                    "sigma_rel_diff_vs_f32": abs(sig - sig32) / abs(sig32), "max_angle_vs_f32": ang,
+                    "ttvc_GBps": round(rq[3] / rq[2] / 1e6, 1)}
+        del Tq
+    del Td
+    torch.cuda.empty_cache()
+    return out
+
+
+def leg_batched(hoscf, synth, reps=1):
+    """4096 order-3 FP32 tensors (dims uniform in {8..96}, planted rank-one,
+    lambda ~ U[1, 20]), greedy rank-8 deflation, one persistent launch."""
+    import numpy as np
+    import torch
+    tensors, _, _ = synth.batched_planted(4096, 5)
+    host = np.concatenate([t.ravel() for t in tensors])
+    buf = torch.from_numpy(host).cuda()
+    views, off = [], 0
+    for t in tensors:
+        views.append(buf[off:off + t.size].view(*t.shape))
+        off += t.size
+    plan = hoscf.BatchPlan(views, R=8, tol=1e-6, max_iter=500)
+    x0 = np.empty(plan.total)
+    for b, dims in enumerate(plan.dims):
+        for r in range(plan.R):
+            o = plan.offsets[b] + r * plan.D[b]
+            x0[o:o + plan.D[b]] = synth.init_factors(dims, 5 * 100003 + b * 17 + r)
+    x0 = torch.from_numpy(x0).cuda()
+    outs = plan.outputs()
+    plan.run(x0, outs)
+    dt, _ = _timed(lambda: plan.run(x0, outs), reps)
+    st = outs[2].cpu().numpy()
+    it = outs[3].cpu().numpy()
+    terms = len(tensors) * plan.R
+    return {"workload": "4096 x order-3 FP32, dims U{8..96}, N(0,1) + U[1,20] planted, rank 8, tol 1e-6",
+            "launch_s": round(dt, 4), "rank_one_solves_per_s": round(terms / dt, 1),
+            "tensors_per_s": round(len(tensors) / dt, 1), "ok_terms": int((st == 0).sum()),
+            "not_converged_terms": int((st == 1).sum()), "mean_iters": round(float(it.mean()), 1),
+            "bytes": int(host.nbytes)}
+
+
+def leg_backward(hoscf, synth, items=4):
+    """Items of the 64 x 256^3 differentiation workload (planted rank-2,
+    lambdas 768 and 512): solve, then dL/dT for L = sigma + w'x (one sweep,
+    the projected adjoint solve, one 67 MB write)."""
+    import numpy as np
+    import torch
+    dims = (256, 256, 256)
+    t_solve = t_bwd = 0.0
+    steps = []
+    for i in range(items):
+        T, _ = synth.planted_cp(dims, [768.0, 512.0], 6000 + i)
+        Td = torch.from_numpy(T).cuda()
+        x0 = torch.from_numpy(synth.init_factors(dims, 7000 + i))
+        w = torch.from_numpy(np.concatenate(synth.loss_weights(dims, 6000 + i))).cuda()
+        opts = hoscf.options(algo="hoscf", tol=1e-6, max_iter=300)
+        hoscf.solve_raw(Td, x0, opts)
+        dt_s, (sig, x, _) = _timed(lambda: hoscf.solve_raw(Td, x0, opts), 1)
+        hoscf.backward(Td, x, sig, 1.0, w)
+        dt_b, (g, mu, info) = _timed(lambda: hoscf.backward(Td, x, sig, 1.0, w, return_info=True), 3)
+        t_solve += dt_s
+        t_bwd += dt_b
+        steps.append(info[0])
+        del Td, g
+    torch.cuda.empty_cache()
+    n = float(np.prod(dims))
+    return {"workload": f"{items} items of 64 x 256^3 FP32 planted rank-2 (768, 512), L = sigma + w'x",
+            "solve_ms": round(t_solve / items * 1e3, 3), "backward_ms": round(t_bwd / items * 1e3, 3),
+            "backward_GBps": round(items * n * 8 / t_bwd / 1e9, 1),
+            "adjoint_lanczos_steps": steps}
 
 
 def main():
@@ -179,6 +298,19 @@ def main():
                      "kernel": "ttvc3_kernel (level-1 pass over T)", "bytes_per_launch": nbytes,
                      "launch_ms": round(ms_root, 5)},
     }
+    if not args.no_extras:
+        del Td
+        torch.cuda.empty_cache()
+        extras = {}
+        for name, fn in (("precision_form", leg_precision), ("batched_form", leg_batched),
+                         ("differentiation_form", leg_backward)):
+            t_leg = time.perf_counter()
+            try:
+                extras[name] = fn(hoscf, synth)
+            except Exception as e:  # a failing extra never hides the main line
+                extras[name] = {"error": f"{type(e).__name__}: {e}"}
+            print(f"[bench] {name} leg: {time.perf_counter() - t_leg:.1f}s", file=sys.stderr, flush=True)
+        out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(T, x0)
     print(json.dumps(out), flush=True)
