@@ -90,6 +90,12 @@ typedef struct {
     int32_t canonical_sign;  /* 1 (default): fix the sign representative every iteration */
     int32_t stall_iters;     /* >0: stop NOT_CONVERGED after this many iterations without a new
                                 lowest residual; 0 = off */
+    double inner_rel;        /* 0 (default): exact inner solves (Ritz residual of the eigen-step and
+                                Galerkin residual of the Rayleigh step at fixed tight floors).
+                                > 0: inexact inner solves, stopped at max(floor, min(1e-3,
+                                inner_rel * res)), res the stopping residual at the iterate; the
+                                returned point still meets tol, but the iterates of a run that
+                                does not converge differ from the exact method's */
 } hoscf_options;
 
 /* Per-solve report. */

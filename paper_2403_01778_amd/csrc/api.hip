@@ -73,6 +73,7 @@ hoscf_options default_options() {
     o.max_refine = 0;
     o.canonical_sign = 1;
     o.stall_iters = 0;
+    o.inner_rel = 0.0;
     return o;
 }
 
@@ -90,6 +91,14 @@ struct SolveLayout {
     double* x = nullptr;   // FP64 iterate (solve) when not aliased to a sweep's unit buffer
     size_t used = 0;
     bool ok = false;
+
+    // Fresh SolveState and workgroup flags (stream-ordered, capture-safe).
+    hipError_t init(hipStream_t s) const {
+        hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return post.reset(s);
+    }
 
     bool build(const hoscf_tensor& T, void* blocks_out, bool solve, int kmax, void* ws, size_t ws_bytes,
                const int64_t* tiling = nullptr) {
@@ -161,8 +170,7 @@ int hoscf_ttvc(const hoscf_tensor* T, const double* x, void* blocks, double* g, 
     SolveLayout lay;
     if (!ws || !lay.build(*T, blocks, false, 1, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
-    HOSCF_TRY(hipGetLastError());
+    HOSCF_TRY(lay.init(s));
     HOSCF_TRY(lay.sweep.run(x, lay.st, s));
     HOSCF_TRY(lay.post.run(kPostEpilogue, lay.sweep.blocks, lay.sweep.blocksT, lay.sweep.xu, g, lay.st, scalars, 0.0, 0.0, 0.0, 1, s));
     return HOSCF_OK;
@@ -181,8 +189,8 @@ int hoscf_profile_sweep(const hoscf_tensor* T, const double* x, void* blocks, do
     double tot = 0.0, k1 = 0.0, k1root = 0.0;
     int rc = HOSCF_OK;
     for (int r = 0; r < reps && rc == HOSCF_OK; ++r) {
-        hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
-        if (hipEventRecord(ev[2 * nn], s) != hipSuccess) rc = HOSCF_HIP_ERROR;
+        if (lay.init(s) != hipSuccess) rc = HOSCF_HIP_ERROR;
+        if (rc == HOSCF_OK && hipEventRecord(ev[2 * nn], s) != hipSuccess) rc = HOSCF_HIP_ERROR;
         if (rc == HOSCF_OK && lay.sweep.run(x, lay.st, s, lay.sweep.num_nodes() ? ev.data() : nullptr) != hipSuccess)
             rc = HOSCF_HIP_ERROR;
         if (rc == HOSCF_OK && lay.post.run(kPostEpilogue, lay.sweep.blocks, lay.sweep.blocksT, lay.sweep.xu, g, lay.st, nullptr, 0.0, 0.0,
@@ -222,7 +230,7 @@ int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* op
     if (!valid_tensor(T) || !x0 || !x_out) return HOSCF_INVALID_ARG;
     const hoscf_options opts = opts_in ? *opts_in : default_options();
     if (opts.algo != 0 && opts.algo != 1) return HOSCF_INVALID_ARG;
-    if (opts.max_iter < 0 || !(opts.tol >= 0.0)) return HOSCF_INVALID_ARG;
+    if (opts.max_iter < 0 || !(opts.tol >= 0.0) || !(opts.inner_rel >= 0.0)) return HOSCF_INVALID_ARG;
     SolveLayout lay;
     if (!ws || !lay.build(*T, nullptr, true, kDefaultKmax, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -239,8 +247,7 @@ int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* op
         return hipStreamSynchronize(s);
     };
     auto body = [&]() -> int {
-        hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
-        HOSCF_TRY(hipGetLastError());
+        HOSCF_TRY(lay.init(s));
         hipLaunchKernelGGL(copy_kernel, dim3(cgrid), dim3(256), 0, s, x0, D, lay.x);
         HOSCF_TRY(hipGetLastError());
         // Phase list: (sweep plan, post plan, tolerance, iteration budget)
@@ -279,7 +286,8 @@ int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* op
             for (;;) {
                 const bool allow = iters < P.max_iter;
                 HOSCF_TRY(P.po->run(allow ? kPostEigen : kPostEpilogue, P.sw->blocks, P.sw->blocksT, x, lay.g, lay.st, nullptr,
-                                    P.tol, eig_tol, eig_tol, opts.canonical_sign, s));
+                                    P.tol, eig_tol, eig_tol, opts.canonical_sign, s, nullptr, nullptr, 0.0, 0.0,
+                                    opts.inner_rel));
                 HOSCF_TRY(fetch());
                 info.lanczos_steps += h->lanczos;
                 last_sigma = h->sigma;
@@ -304,7 +312,7 @@ int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* op
                 if (P.lp) info.lp_sweeps++;
                 if (opts.algo == 1) {
                     HOSCF_TRY(P.po->run(kPostRqi, P.sw->blocks, P.sw->blocksT, x, lay.g, lay.st, nullptr, P.tol, eig_tol, solve_tol,
-                                        opts.canonical_sign, s));
+                                        opts.canonical_sign, s, nullptr, nullptr, 0.0, 0.0, opts.inner_rel));
                     HOSCF_TRY(fetch());
                     info.lanczos_steps += h->lanczos;
                     if (h->nonfinite) return HOSCF_NONFINITE;
@@ -347,8 +355,7 @@ int hoscf_backward(const hoscf_tensor* T, const double* x, double sigma, double 
     if (!ws || !lay.build(*T, nullptr, true, kDefaultKmax, ws, ws_bytes)) return HOSCF_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const BlockMap& map = lay.sweep.map;
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
-    HOSCF_TRY(hipGetLastError());
+    HOSCF_TRY(lay.init(s));
     // blocks of M = (N-1) J at the unit factors (one read of T)
     HOSCF_TRY(lay.sweep.run(x, lay.st, s));
     double* mu = mu_out ? mu_out : lay.x;
@@ -389,8 +396,7 @@ int hoscf_ttvc_backward(const hoscf_tensor* T, const double* x, const void* bloc
     hipStream_t s = static_cast<hipStream_t>(stream);
     const BlockMap& map = lay.sweep.map;
     const unsigned cgrid = (unsigned)std::min<int64_t>((map.D + 255) / 256, 1024);
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, lay.st);
-    HOSCF_TRY(hipGetLastError());
+    HOSCF_TRY(lay.init(s));
     if (grad_x) {
         // blocks given: unit factors and transposed copies only; else one sweep
         HOSCF_TRY(blocks ? lay.sweep.prepare(x, lay.st, s) : lay.sweep.run(x, lay.st, s));

@@ -38,7 +38,7 @@ struct BatchItem {
 struct BatchArgs {
     const BatchItem* items;
     int B, R;
-    double tol, eig_tol;
+    double tol, eig_tol, inner_rel;
     int max_iter, canonical;
     const double* x0;
     double* x_out;
@@ -282,6 +282,8 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                 ++iters;
 
                 // ---- eigen-step: Lanczos on J = M/2 from x~ = u/sqrt(3) ----
+                // (inexact when inner_rel > 0: accurate relative to the residual)
+                const double eig_tol = fmax(a.eig_tol, a.inner_rel > 0.0 ? fmin(1e-3, a.inner_rel * res) : 0.0);
                 double* w = L.a.vec;                 // [D]
                 double* vj = L.a.vec + kBatchMaxD;   // staged V_j
                 const double is3 = 1.0 / sqrt(3.0);
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                                     for (int i = 0; i < m; ++i) L.s[i] /= nrm;
                                 }
                                 const double ritz = beta * fabs(L.s[m - 1]);
-                                L.stop = (ritz <= a.eig_tol * fmax(normJ, fabs(th))) || invariant || m == kBatchKmax;
+                                L.stop = (ritz <= eig_tol * fmax(normJ, fabs(th))) || invariant || m == kBatchKmax;
                             }
                         }
                         __syncthreads();
@@ -467,7 +469,7 @@ int hoscf_batch_plan_create(int B, const hoscf_tensor* descs, int R, const hoscf
     o.max_iter = 500;
     o.canonical_sign = 1;
     if (opts) o = *opts;
-    if (o.algo != 0 || !(o.tol >= 0.0) || o.max_iter < 0) return HOSCF_INVALID_ARG;
+    if (o.algo != 0 || !(o.tol >= 0.0) || o.max_iter < 0 || !(o.inner_rel >= 0.0)) return HOSCF_INVALID_ARG;
     std::vector<BatchItem> items((size_t)B);
     int64_t xoff = 0;
     for (int b = 0; b < B; ++b) {
@@ -532,6 +534,7 @@ int hoscf_solve_batched(const hoscf_plan* plan, const double* x0, double* x_out,
     a.R = plan->R;
     a.tol = plan->opts.tol;
     a.eig_tol = std::min(1e-8, std::max(1e-13, 1e-3 * plan->opts.tol));
+    a.inner_rel = plan->opts.inner_rel;
     a.max_iter = plan->opts.max_iter;
     a.canonical = plan->opts.canonical_sign;
     a.x0 = x0;

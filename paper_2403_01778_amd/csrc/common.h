@@ -56,6 +56,7 @@ struct SolveState {
     int32_t barrier_timeout;
     int32_t pad;
     unsigned bar[2];     // grid barrier: arrival count, generation
+    uint64_t epoch;      // last flag value used by the post-sweep kernel's workgroup flags
     // phase timestamps of the last post-sweep launch per kind (epilogue-only
     // at [0..15], eigen / Rayleigh at [16..31]; constant 100 MHz clock):
     // +0 start, +1 J x done, +2 sigma reduced, +3 residual reduced,

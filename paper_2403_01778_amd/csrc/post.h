@@ -31,6 +31,10 @@ struct PostArgs {
     int seg_src[kMaxOrder][kMaxOrder];  // 0 = blocks, 1 = blocksT
     int mode;
     double tol, eig_tol, solve_tol;
+    // Inexact inner solves: the eigen-step's Ritz tolerance and the Rayleigh
+    // step's Galerkin tolerance are max(floor, min(1e-3, inner_rel * res)),
+    // res the stopping residual at the iterate (0 = fixed floors).
+    double inner_rel;
     int kmax;
     int canonical;
     int nwg;
@@ -39,6 +43,7 @@ struct PostArgs {
     double* g;       // [D] mode vectors out
     SolveState* st;
     unsigned* bar;   // grid barrier words (inside st)
+    uint64_t* flags; // [nwg] per-workgroup epoch flags (zeroed by reset())
     double* scalars_out;
     double* V;       // [(kmax+1) * D] Lanczos basis
     double* w;       // [D]
@@ -53,7 +58,10 @@ class PostPlan {
     bool build(const BlockMap& map, bool f64_blocks, int kmax, int max_wg, Arena& ar);
     hipError_t run(int mode, const void* blocks, const void* blocksT, double* x, double* g, SolveState* st, double* scalars,
                    double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s,
-                   const double* rhs = nullptr, double* out = nullptr, double coef = 0.0, double shift = 0.0) const;
+                   const double* rhs = nullptr, double* out = nullptr, double coef = 0.0, double shift = 0.0,
+                   double inner_rel = 0.0) const;
+    // Zero the workgroup flags; call whenever the SolveState is (re)initialised.
+    hipError_t reset(hipStream_t s) const;
     PostArgs a{};
     bool f64 = false;
 };

@@ -83,40 +83,6 @@ __device__ __forceinline__ void st_ag(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ---------------------------------------------------------------------------
-// Grid-wide barrier for a co-resident grid (cooperative launch).  Arrival is a
-// device-scope atomic add; the last arrival advances the generation word.
-// Waiting is bounded: after ~2^26 polls the barrier gives up and raises
-// `timeout` so the kernel still runs to its end.
-// ---------------------------------------------------------------------------
-__device__ void grid_barrier(unsigned* bar, unsigned nwg, int* timeout) {
-    __syncthreads();
-    if (nwg == 1) return;
-    if (threadIdx.x == 0) {
-        unsigned* count = bar;
-        unsigned* gen = bar + 1;
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // release: this workgroup's stores are visible before its arrival is
-        const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nwg - 1) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned polls = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (++polls > (1u << 28)) {
-                    *timeout = 1;
-                    break;
-                }
-            }
-        }
-        // shared data is read with device-coherent loads after this point, so
-        // only the workgroup's own ordering is needed here
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-    __syncthreads();
-}
-
 struct Lds {
     double al[kKmaxLds], be[kKmaxLds], b2[kKmaxLds];
     double s[kKmaxLds];       // Ritz vector / Galerkin solution of T_m
@@ -128,15 +94,43 @@ struct Lds {
     int64_t xoff[kMaxOrder + 1];
     double fl[kMaxOrder], inv[kMaxOrder];
     double theta, ritz;
+    uint64_t epoch0;
     int stop, ok, timeout;
 };
+
+// Grid-wide synchronisation point number `epoch` of a co-resident grid: each
+// workgroup publishes `epoch` in its own flag (release, after the workgroup
+// barrier has retired its stores) and then waits until every flag has
+// reached it.  Flags only grow (epochs continue across launches through
+// SolveState::epoch), so no flag is ever reset inside a launch and a fast
+// workgroup that publishes the next epoch early cannot be missed.  Data
+// exchanged between workgroups is written and read with device-coherent
+// accesses, so only the workgroup's own ordering is needed after the wait.
+// Waiting is bounded: on timeout the workgroup raises `timeout` and goes on.
+__device__ void flag_barrier(const PostArgs& a, uint64_t epoch, int* timeout) {
+    __syncthreads();
+    if (a.nwg == 1) return;
+    if (threadIdx.x == 0) __hip_atomic_store(a.flags + blockIdx.x, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    for (int w = threadIdx.x; w < a.nwg; w += BS) {
+        unsigned polls = 0;
+        while (__hip_atomic_load(a.flags + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            if (++polls > (1u << 22)) {
+                *timeout = 1;
+                break;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __syncthreads();
+}
+
 
 // All-reduce of K per-workgroup partials held in L.mine (alternating
 // buffers, so a fast workgroup never overwrites partials another is still
 // reading).  After the barrier every thread gathers partials with eight loads
 // in flight into LDS (`stage`, kVecLds doubles), then thread k sums column k
 // over the workgroups in workgroup order.  Totals land in L.hsum.
-__device__ void allreduce(const PostArgs& a, int K, int& parity, Lds& L, double* stage) {
+__device__ void allreduce(const PostArgs& a, int K, int& parity, uint64_t& sync, Lds& L, double* stage) {
     if (a.nwg == 1) {
         __syncthreads();
         for (int k = threadIdx.x; k < K; k += BS) L.hsum[k] = L.mine[k];
@@ -147,7 +141,7 @@ __device__ void allreduce(const PostArgs& a, int K, int& parity, Lds& L, double*
     parity ^= 1;
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += BS) st_ag(buf + (size_t)blockIdx.x * a.RK + k, L.mine[k]);
-    grid_barrier(a.bar, a.nwg, &L.timeout);
+    flag_barrier(a, ++sync, &L.timeout);
     const int kc = std::max(1, std::min(K, kVecLds / a.nwg));  // columns per LDS pass
     for (int k0 = 0; k0 < K; k0 += kc) {
         const int kn = std::min(kc, K - k0);
@@ -408,9 +402,13 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     const double inv_n1 = 1.0 / (double)(a.N - 1);
     const double inv_sqrtN = 1.0 / sqrt((double)a.N);
     int parity = 0;
-    if (tid == 0) L.timeout = 0;
+    if (tid == 0) {
+        L.timeout = 0;
+        L.epoch0 = __hip_atomic_load(&a.st->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (tid <= a.N) L.xoff[tid] = a.xoff[tid];
     __syncthreads();
+    uint64_t sync = L.epoch0;  // synchronisation points of this launch continue from here
     const bool tr = blockIdx.x == 0 && tid == 0;
     uint64_t* trace = a.st->trace + (a.mode == kPostEpilogue ? 0 : 16);
 #define HOSCF_MARK(k) \
@@ -425,7 +423,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     for (int64_t r = r_lo + tid; r < r_hi && r < L.xoff[1]; r += BS) s0 = fma(a.x[r], a.g[r], s0);
     wg_to_mine(s0, 0, L);
     wg_to_mine(fro, 1, L);
-    allreduce(a, 2, parity, L, vlds);
+    allreduce(a, 2, parity, sync, L, vlds);
     HOSCF_MARK(2);
     const double sigma = L.hsum[0];
     const double normJ = sqrt(L.hsum[1]) * inv_n1;
@@ -435,7 +433,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         rr = fma(e, e, rr);
     }
     wg_to_mine(rr, 0, L);
-    allreduce(a, 1, parity, L, vlds);
+    allreduce(a, 1, parity, sync, L, vlds);
     HOSCF_MARK(3);
     const double den = normJ + fabs(sigma);
     const bool zero = !(den > 0.0);  // J = 0: T vanishes on the current factors
@@ -459,6 +457,11 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         }
     }
     bool done = a.mode == kPostEpilogue || nonfinite || zero || (a.mode == kPostEigen && res <= a.tol);
+    // inner tolerances: far from convergence the eigenvector (or the shifted
+    // solve) only needs to be accurate relative to the current residual
+    const double loose = a.inner_rel > 0.0 ? fmin(1e-3, a.inner_rel * res) : 0.0;
+    const double eig_tol = fmax(a.eig_tol, loose);
+    const double solve_tol = fmax(a.solve_tol, loose);
     if (a.mode == kPostMatvec) {
         // out = (N-1) J rhs + coef g over own rows (g of this workgroup's rows)
         matvec_rows<B, false>(a, a.rhs, a.out, 1.0, false, r_lo, r_hi, vlds);
@@ -481,7 +484,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         double rr2 = 0.0;
         for (int64_t r = r_lo + tid; r < r_hi; r += BS) rr2 = fma(a.rhs[r], a.rhs[r], rr2);
         wg_to_mine(rr2, a.N, L);
-        allreduce(a, a.N + 1, parity, L, vlds);
+        allreduce(a, a.N + 1, parity, sync, L, vlds);
         double nb2 = L.hsum[a.N];
         for (int n = 0; n < a.N; ++n) nb2 -= L.hsum[n] * L.hsum[n];
         if (!(nb2 > 0.0)) {
@@ -505,7 +508,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 st_ag(V + r, a.x[r] * inv_sqrtN);
                 w[r] = a.g[r] * inv_sqrtN;  // J x~ = [g_n] / sqrt(N)
             }
-        grid_barrier(a.bar, a.nwg, &L.timeout);  // V_0 complete before any matvec reads it
+        flag_barrier(a, ++sync, &L.timeout);  // V_0 complete before any matvec reads it
         const int NP = proj ? a.N : 0;           // projection components per reduction
         bool stop = false;
         for (int j = 0; j < kmax && !stop; ++j) {
@@ -517,7 +520,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             // pass 1: h_i = V_i . w over own rows
             own_dots(V, w, D, j, r_lo, r_hi, L.mine);
             if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 1, L);
-            allreduce(a, j + 1 + NP, parity, L, vlds);
+            allreduce(a, j + 1 + NP, parity, sync, L, vlds);
             if (j == 1) HOSCF_MARK(10);
             own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
             if (proj) own_xsub(a, w, L.hsum + j + 1, r_lo, r_hi, L);
@@ -531,7 +534,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             nn = wg_sum(nn, L.red4);
             if (tid == 0) L.mine[j + 1] = nn;
             if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 2, L);
-            allreduce(a, j + 2 + NP, parity, L, vlds);
+            allreduce(a, j + 2 + NP, parity, sync, L, vlds);
             if (j == 1) HOSCF_MARK(12);
             double corr2 = 0.0;
             for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                             }
                             L.theta = th;
                             L.ritz = beta * fabs(sv[m - 1]);
-                            L.stop = (L.ritz <= a.eig_tol * fmax(normJ, fabs(th))) || invariant || m == kmax;
+                            L.stop = (L.ritz <= eig_tol * fmax(normJ, fabs(th))) || invariant || m == kmax;
                         }
                     }
                 } else if (tid == 0) {
@@ -592,7 +595,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                     // small in absolute terms means z_m is the solve's answer, not merely a
                     // near-null vector of J - rho I.
                     L.ritz = ok ? beta * fabs(t[m - 1]) : INFINITY;
-                    L.stop = (m >= 2 && ok && L.ritz <= a.solve_tol) || invariant || m == kmax;
+                    L.stop = (m >= 2 && ok && L.ritz <= solve_tol) || invariant || m == kmax;
                 }
                 __syncthreads();
                 stop = L.stop != 0;
@@ -602,7 +605,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 const double ib = 1.0 / beta;
                 double* Vn = V + (size_t)(j + 1) * D;
                 for (int64_t r = r_lo + tid; r < r_hi; r += BS) st_ag(Vn + r, w[r] * ib);
-                grid_barrier(a.bar, a.nwg, &L.timeout);
+                flag_barrier(a, ++sync, &L.timeout);
             }
             if (j == 0) HOSCF_MARK(4);
             if (j == 1) HOSCF_MARK(6);
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         if (blockIdx.x == 0 && tid == 0) {
             a.st->lanczos = m;
             a.st->ritz_res = L.ritz;
-            a.st->eig_unconverged = (!L.ok || L.ritz > a.solve_tol) ? 1 : 0;
+            a.st->eig_unconverged = (!L.ok || L.ritz > solve_tol) ? 1 : 0;
         }
         done = true;
     }
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         a.st->rho = rho;
         a.st->theta = L.theta;
         a.st->ritz_res = L.ritz;
-        if (a.mode == kPostEigen) a.st->eig_unconverged = (L.ritz > a.eig_tol * fmax(normJ, fabs(L.theta))) ? 1 : 0;
+        if (a.mode == kPostEigen) a.st->eig_unconverged = (L.ritz > eig_tol * fmax(normJ, fabs(L.theta))) ? 1 : 0;
     }
     if (accept) {
         // y = V_m s (own rows), then per-block norm and largest-|entry|
@@ -714,7 +717,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             double* buf = a.red + (size_t)parity * a.nwg * a.RK;
             parity ^= 1;
             for (int k = tid; k < 4 * N; k += BS) st_ag(buf + (size_t)blockIdx.x * a.RK + k, L.mine[k]);
-            grid_barrier(a.bar, a.nwg, &L.timeout);
+            flag_barrier(a, ++sync, &L.timeout);
             if (tid == 0) {
                 for (int n = 0; n < N; ++n) {
                     double sn = 0.0, v = -1.0, sg = 0.0, ix = 1e300;
@@ -765,6 +768,9 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         }
     }
     if (tid == 0 && L.timeout) a.st->barrier_timeout = 1;
+    // every workgroup has read epoch0 before any could pass the first flag
+    // wait, so workgroup 0 may advance it for the next launch now
+    if (blockIdx.x == 0 && tid == 0) __hip_atomic_store(&a.st->epoch, sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     HOSCF_MARK(8);
     if (tr) trace[9] = (uint64_t)m;
 #undef HOSCF_MARK
@@ -808,13 +814,25 @@ bool PostPlan::build(const BlockMap& map, bool f64_blocks, int kmax, int max_wg,
     a.V = ar.take<double>((size_t)(a.kmax + 1) * map.D);
     a.w = ar.take<double>(map.D);
     a.red = ar.take<double>((size_t)2 * nwg * a.RK);
+    a.flags = ar.take<uint64_t>((size_t)nwg);
     return ar.ok;
+}
+
+__global__ void zero_flags_kernel(uint64_t* f, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) f[i] = 0;
+}
+
+hipError_t PostPlan::reset(hipStream_t s) const {
+    if (!a.flags) return hipSuccess;
+    hipLaunchKernelGGL(zero_flags_kernel, dim3(1), dim3(256), 0, s, a.flags, a.nwg);
+    return hipGetLastError();
 }
 
 hipError_t PostPlan::run(int mode, const void* blocks, const void* blocksT, double* x, double* g, SolveState* st, double* scalars,
                          double tol, double eig_tol, double solve_tol, int canonical, hipStream_t s,
-                         const double* rhs, double* out, double coef, double shift) const {
+                         const double* rhs, double* out, double coef, double shift, double inner_rel) const {
     PostArgs args = a;
+    args.inner_rel = inner_rel;
     args.rhs = rhs;
     args.out = out;
     args.coef = coef;

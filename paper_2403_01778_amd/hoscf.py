@@ -35,7 +35,7 @@ class HoscfTensor(ctypes.Structure):
 class HoscfOptions(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("tol_lp", ctypes.c_double), ("max_refine", ctypes.c_int32), ("canonical_sign", ctypes.c_int32),
-                ("stall_iters", ctypes.c_int32)]
+                ("stall_iters", ctypes.c_int32), ("inner_rel", ctypes.c_double)]
 
 
 class HoscfInfo(ctypes.Structure):
@@ -244,7 +244,8 @@ class SolveInfo:
 
 
 def options(algo: str = "hoscf", tol: float = 1e-10, max_iter: int = 500, tol_lp: float = 1e-3,
-            max_refine: int = 0, canonical_sign: bool = True, stall_iters: int = 0) -> HoscfOptions:
+            max_refine: int = 0, canonical_sign: bool = True, stall_iters: int = 0,
+            inner_rel: float = 0.0) -> HoscfOptions:
     o = HoscfOptions()
     o.algo = {"hoscf": 0, "ihoscf": 1}[algo]
     o.tol = float(tol)
@@ -253,6 +254,7 @@ def options(algo: str = "hoscf", tol: float = 1e-10, max_iter: int = 500, tol_lp
     o.max_refine = int(max_refine)
     o.canonical_sign = 1 if canonical_sign else 0
     o.stall_iters = int(stall_iters)
+    o.inner_rel = float(inner_rel)
     return o
 
 
@@ -370,7 +372,7 @@ class BatchPlan:
     Keeps the tensors alive; frees the plan on deletion."""
 
     def __init__(self, tensors: Sequence[torch.Tensor], R: int, tol: float = 1e-6, max_iter: int = 500,
-                 canonical_sign: bool = True):
+                 canonical_sign: bool = True, inner_rel: float = 0.0):
         self.tensors = [t.contiguous() for t in tensors]
         self.R = int(R)
         self.dims = [tuple(int(d) for d in t.shape) for t in self.tensors]
@@ -384,7 +386,7 @@ class BatchPlan:
         descs = (HoscfTensor * max(1, len(self.tensors)))()
         for i, t in enumerate(self.tensors):
             descs[i] = describe(t)
-        opts = options(algo="hoscf", tol=tol, max_iter=max_iter, canonical_sign=canonical_sign)
+        opts = options(algo="hoscf", tol=tol, max_iter=max_iter, canonical_sign=canonical_sign, inner_rel=inner_rel)
         h = ctypes.c_void_p()
         _check(_lib.hoscf_batch_plan_create(len(self.tensors), descs, self.R, ctypes.byref(opts), ctypes.byref(h)),
                "hoscf_batch_plan_create")

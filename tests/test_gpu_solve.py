@@ -158,3 +158,20 @@ def test_fp64_multi_workgroup_eigen(lib, algo):
     sig, x, info = gpu_solve(lib, T, x0, algo, 1e-11, 300)
     assert info.status == ref.status == 0
     assert_parity(T, x, sig, ref, 1e-12)
+
+
+@pytest.mark.parametrize("algo", ["hoscf", "ihoscf"])
+def test_inexact_inner_solves_same_point(lib, algo):
+    """inner_rel > 0 (inner solves accurate relative to the residual) reaches
+    the same converged KKT point as the exact method, FP64 bar."""
+    T, _ = synth.planted_rank_one((30, 25, 20, 15), 40.0, 61, dtype=np.float64)
+    x0 = synth.init_factors(T.shape, 61)
+    ref = oracle.hoscf(T, x0, algo=algo, tol=1e-12, max_iter=1000)
+    assert ref.status == oracle.OK
+    sig, x, info = gpu_solve(lib, T, x0, algo, 1e-12, 1000, inner_rel=1e-3)
+    sig_e, x_e, info_e = gpu_solve(lib, T, x0, algo, 1e-12, 1000)
+    print(f"[inexact] {algo}: lanczos {info.lanczos_steps} vs exact {info_e.lanczos_steps}; "
+          f"iters {info.iters} vs {info_e.iters}", flush=True)
+    assert info.status == 0
+    assert_parity(T, x, sig, ref, 1e-12)
+    assert info.lanczos_steps <= info_e.lanczos_steps
