@@ -67,6 +67,7 @@ struct BatchLds {
     double h[kBatchKmax + 8];
     double red[16];
     double defl[16 * 3];   // per previous term: sigma_s * (x_{s,k}' u_k) for the three blocks
+    double xi[16];         // mode-1 entries x_{s,1}[i] of the previous terms at the current slab
     double sc[8];
     int item, stop;
 };
@@ -184,6 +185,20 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                     const int e = tid + q * BT;
                     cur[q] = item.T[e < n23 ? e : 0];
                 }
+                // deflation: the row threads keep their fixed factor entries of the
+                // previous terms in registers (x_{s,2}[j] for A12 rows, x_{s,3}[k]
+                // for A13 rows); the mode-1 entries x_{s,1}[i] of the current slab
+                // are staged in LDS with the slab
+                constexpr int RMAX = 16;
+                double cfix[RMAX];
+                {
+                    const int col = tid < I2 ? I1 + tid : (tid >= BT / 2 && tid < BT / 2 + I3 ? I1 + I2 + tid - BT / 2 : -1);
+#pragma unroll
+                    for (int s2 = 0; s2 < RMAX; ++s2) {
+                        const double* xs = a.x_out + item.xoff + (int64_t)s2 * D;
+                        cfix[s2] = (s2 < r && col >= 0) ? xs[col] : 0.0;
+                    }
+                }
                 double fro = 0.0;
                 for (int i = 0; i < I1; ++i) {
 #pragma unroll
@@ -191,6 +206,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                         const int e = tid + q * BT;
                         if (e < n23) L.a.slab[e] = cur[q];
                     }
+                    if (tid < r) L.xi[tid] = a.x_out[item.xoff + (int64_t)tid * D + i];
                     const int inext = i + 1 < I1 ? i + 1 : i;
                     const float* Tn = item.T + (int64_t)inext * n23;
 #pragma unroll
@@ -208,10 +224,9 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                         double acc = 0.0;
                         for (int k = 0; k < I3; ++k) acc = fma((double)L.a.slab[j * I3 + k], L.u[I1 + I2 + k], acc);
                         double corr = 0.0;
-                        for (int s = 0; s < r; ++s) {
-                            const double* xs = a.x_out + item.xoff + (int64_t)s * D;
-                            corr = fma(L.defl[3 * s + 0] * xs[i], xs[I1 + j], corr);
-                        }
+#pragma unroll
+                        for (int s2 = 0; s2 < RMAX; ++s2)
+                            if (s2 < r) corr = fma(L.defl[3 * s2 + 0] * L.xi[s2], cfix[s2], corr);
                         const float v = (float)(acc - corr);
                         A12[i * I2 + j] = v;
                         fro = fma((double)v, (double)v, fro);
@@ -220,10 +235,9 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                         double acc = 0.0;
                         for (int j = 0; j < I2; ++j) acc = fma((double)L.a.slab[j * I3 + k], L.u[I1 + j], acc);
                         double corr = 0.0;
-                        for (int s = 0; s < r; ++s) {
-                            const double* xs = a.x_out + item.xoff + (int64_t)s * D;
-                            corr = fma(L.defl[3 * s + 1] * xs[i], xs[I1 + I2 + k], corr);
-                        }
+#pragma unroll
+                        for (int s2 = 0; s2 < RMAX; ++s2)
+                            if (s2 < r) corr = fma(L.defl[3 * s2 + 1] * L.xi[s2], cfix[s2], corr);
                         const float v = (float)(acc - corr);
                         A13[i * I3 + k] = v;
                         fro = fma((double)v, (double)v, fro);

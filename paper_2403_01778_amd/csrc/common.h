@@ -61,8 +61,9 @@ struct SolveState {
     // at [0..15], eigen / Rayleigh at [16..31]; constant 100 MHz clock):
     // +0 start, +1 J x done, +2 sigma reduced, +3 residual reduced,
     // +4 Lanczos step 0 done, +5 step 1 J v done, +6 step 1 done,
-    // +7 Lanczos done, +8 end, +9 Lanczos steps; within step 1:
-    // +10 first reduction, +11 first update, +12 second reduction, +13 check
+    // +7 Lanczos done, +8 end, +9 Lanczos steps; summed over the steps:
+    // +10 J products, +11 first pass, +12 second pass, +13 checks,
+    // +14 new basis vector and barrier
     uint64_t trace[32];
 };
 

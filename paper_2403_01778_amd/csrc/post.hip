@@ -197,9 +197,7 @@ __device__ void stage_to_lds(double* dst, const double* src, int64_t n) {
     }
 }
 
-// Raw (N-1) J v for the workgroup's own rows, written to out[r]; returns the
-// thread's share of the sum over own rows of ||row||^2 when want_fro.  v is
-// staged in LDS when it fits; each lane keeps RW rows x 4 loads in flight.
+// 16-byte vectors of the stored block type, widened to FP64.
 template <typename B>
 struct Vec16;
 template <>
@@ -304,8 +302,25 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
 // h_i = sum over own rows of V_i[r] w[r] for i <= j into mine[i].  Wave
 // `wave` takes basis vectors i = wave + 4u (u < 8) per round, lanes stride
 // over the own rows; the eight loads per lane are independent.
-__device__ void own_dots(const double* V, const double* w, int64_t D, int j, int64_t r_lo, int64_t r_hi,
-                         double* mine) {
+// The Krylov basis: every vector in global memory (the J products read all
+// of it), and the workgroup's own rows of the first `cap` vectors also in
+// LDS, where the reorthogonalisation passes (own rows only) read them.
+constexpr int kVownLds = 8960;  // doubles
+struct OwnV {
+    double* V;      // [(kmax+1) * D]
+    double* lds;    // [cap * rows]
+    int64_t D, r_lo;
+    int rows, cap;
+    __device__ double get(int i, int64_t r) const {
+        return i < cap ? lds[i * rows + (int)(r - r_lo)] : ld_ag(V + (size_t)i * D + r);
+    }
+    __device__ void put(int i, int64_t r, double v) const {
+        st_ag(V + (size_t)i * D + r, v);
+        if (i < cap) lds[i * rows + (int)(r - r_lo)] = v;
+    }
+};
+
+__device__ void own_dots(const OwnV& ov, const double* w, int j, int64_t r_lo, int64_t r_hi, double* mine) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NW = BS / 64;
@@ -319,7 +334,7 @@ __device__ void own_dots(const double* V, const double* w, int64_t D, int j, int
             for (int u = 0; u < 8; ++u) {
                 const int i = i0 + u * NW;
                 const int ic = i <= j ? i : 0;
-                const double vi = ld_ag(V + (size_t)ic * D + r);
+                const double vi = ov.get(ic, r);
                 h[u] = fma(i <= j ? vi : 0.0, wr, h[u]);
             }
         }
@@ -335,7 +350,7 @@ __device__ void own_dots(const double* V, const double* w, int64_t D, int j, int
 // out[r] = sum_{i<m} c_i V_i[r] over own rows: the four waves take interleaved
 // quarters of i (eight independent loads per lane per round), partial sums
 // meet in LDS in a fixed order.  Returns through `out` (may alias nothing read).
-__device__ void own_combine(const double* V, int64_t D, int m, int64_t r_lo, int64_t r_hi, const double* c,
+__device__ void own_combine(const OwnV& ov, int m, int64_t r_lo, int64_t r_hi, const double* c,
                             double* part /* LDS [NW][64] */, double* out, bool subtract) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -351,7 +366,7 @@ __device__ void own_combine(const double* V, int64_t D, int m, int64_t r_lo, int
             for (int u = 0; u < 8; ++u) {
                 const int i = i0 + u;
                 const int ic = i < m ? i : 0;
-                const double vi = ld_ag(V + (size_t)ic * D + rc);
+                const double vi = ov.get(ic, rc);
                 acc[u] = fma(i < m ? c[ic] : 0.0, vi, acc[u]);
             }
         }
@@ -396,6 +411,7 @@ template <typename B>
 __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     __shared__ Lds L;
     __shared__ double vlds[kVecLds];
+    __shared__ double vown_lds[kVownLds];
     const int tid = threadIdx.x;
     const int64_t D = a.D;
     const int64_t r_lo = D * blockIdx.x / a.nwg, r_hi = D * (blockIdx.x + 1) / a.nwg;
@@ -414,6 +430,20 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
 #define HOSCF_MARK(k) \
     if (tr) trace[k] = __builtin_amdgcn_s_memrealtime()
     HOSCF_MARK(0);
+    // per-phase time summed over the Lanczos steps: [10] J products, [11] first
+    // reorthogonalisation pass, [12] second pass and norm, [13] convergence
+    // checks, [14] new basis vector and its barrier
+    uint64_t tprev = 0;
+    if (tr) {
+        for (int k = 10; k < 15; ++k) trace[k] = 0;
+        tprev = __builtin_amdgcn_s_memrealtime();
+    }
+#define HOSCF_ACC(k)                                           \
+    if (tr) {                                                  \
+        const uint64_t now_ = __builtin_amdgcn_s_memrealtime(); \
+        trace[k] += now_ - tprev;                              \
+        tprev = now_;                                          \
+    }
 
     // ---- A. g, sigma, ||J||_F, residual -------------------------------------
     double fro = matvec_rows<B, false>(a, a.x, a.g, inv_n1, true, r_lo, r_hi, vlds);
@@ -474,6 +504,13 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     // ---- B. Lanczos from x~ --------------------------------------------------
     const int kmax = a.kmax;
     double* V = a.V;
+    OwnV ov;
+    ov.V = V;
+    ov.lds = vown_lds;
+    ov.D = D;
+    ov.r_lo = r_lo;
+    ov.rows = (int)(r_hi - r_lo);
+    ov.cap = ov.rows > 0 ? (int)std::min<int64_t>(kmax + 1, kVownLds / ov.rows) : 0;
     double* w = a.w;
     int m = 0;
     double rho = 0.0;
@@ -498,49 +535,49 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
                 const int64_t hi = r_hi < L.xoff[n + 1] ? r_hi : L.xoff[n + 1];
                 const double cn = L.hsum[n];
-                for (int64_t r = lo + tid; r < hi; r += BS) st_ag(V + r, fma(-cn, a.x[r], a.rhs[r]) * ib);
+                for (int64_t r = lo + tid; r < hi; r += BS) ov.put(0, r, fma(-cn, a.x[r], a.rhs[r]) * ib);
             }
         }
     }
     if (!done) {
         if (!proj)
             for (int64_t r = r_lo + tid; r < r_hi; r += BS) {
-                st_ag(V + r, a.x[r] * inv_sqrtN);
+                ov.put(0, r, a.x[r] * inv_sqrtN);
                 w[r] = a.g[r] * inv_sqrtN;  // J x~ = [g_n] / sqrt(N)
             }
         flag_barrier(a, ++sync, &L.timeout);  // V_0 complete before any matvec reads it
         const int NP = proj ? a.N : 0;           // projection components per reduction
         bool stop = false;
+        HOSCF_ACC(14);
         for (int j = 0; j < kmax && !stop; ++j) {
             if (j > 0 || proj) {
                 matvec_rows<B, true>(a, V + (size_t)j * D, w, inv_n1, false, r_lo, r_hi, vlds);
                 __syncthreads();
                 if (j == 1) HOSCF_MARK(5);
             }
+            HOSCF_ACC(10);
             // pass 1: h_i = V_i . w over own rows
-            own_dots(V, w, D, j, r_lo, r_hi, L.mine);
+            own_dots(ov, w, j, r_lo, r_hi, L.mine);
             if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 1, L);
             allreduce(a, j + 1 + NP, parity, sync, L, vlds);
-            if (j == 1) HOSCF_MARK(10);
-            own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+            own_combine(ov, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
             if (proj) own_xsub(a, w, L.hsum + j + 1, r_lo, r_hi, L);
-            if (j == 1) HOSCF_MARK(11);
             if (tid == 0) L.al[j] = L.hsum[j];
             __syncthreads();
+            HOSCF_ACC(11);
             // pass 2: h'_i and ||w||^2
-            own_dots(V, w, D, j, r_lo, r_hi, L.mine);
+            own_dots(ov, w, j, r_lo, r_hi, L.mine);
             double nn = 0.0;
             for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
             nn = wg_sum(nn, L.red4);
             if (tid == 0) L.mine[j + 1] = nn;
             if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 2, L);
             allreduce(a, j + 2 + NP, parity, sync, L, vlds);
-            if (j == 1) HOSCF_MARK(12);
             double corr2 = 0.0;
             for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
             for (int i = 0; i < NP; ++i) corr2 = fma(L.hsum[j + 2 + i], L.hsum[j + 2 + i], corr2);
             const double beta = sqrt(fmax(L.hsum[j + 1] - corr2, 0.0));
-            own_combine(V, D, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+            own_combine(ov, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
             if (proj) own_xsub(a, w, L.hsum + j + 2, r_lo, r_hi, L);
             if (tid == 0) {
                 L.al[j] += L.hsum[j];
@@ -548,6 +585,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 L.b2[j] = beta * beta;
             }
             __syncthreads();
+            HOSCF_ACC(12);
             m = j + 1;
             rho = proj ? a.shift * inv_n1 : L.al[0];
             const bool invariant = beta <= 1e-14 * normJ;
@@ -567,7 +605,8 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                             double* sv = L.s;
                             for (int i = 0; i < m; ++i) sv[i] = 1.0;
                             const double zrep = 2.220446049250313e-16 * fmax(fabs(lmin), fabs(lmax)) + 1e-300;
-                            for (int it = 0; it < 3; ++it) {
+                            // the shift is accurate to rounding: two inverse iterations suffice
+                            for (int it = 0; it < 2; ++it) {
                                 tri_solve(L.al, L.be, m, th, sv, zrep, L.tri, L.tri + kKmaxLds, L.tri + 2 * kKmaxLds,
                                           L.tri + 3 * kKmaxLds);
                                 double nrm = 0.0;
@@ -600,13 +639,13 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 __syncthreads();
                 stop = L.stop != 0;
             }
-            if (j == 1) HOSCF_MARK(13);
+            HOSCF_ACC(13);
             if (!stop) {
                 const double ib = 1.0 / beta;
-                double* Vn = V + (size_t)(j + 1) * D;
-                for (int64_t r = r_lo + tid; r < r_hi; r += BS) st_ag(Vn + r, w[r] * ib);
+                for (int64_t r = r_lo + tid; r < r_hi; r += BS) ov.put(j + 1, r, w[r] * ib);
                 flag_barrier(a, ++sync, &L.timeout);
             }
+            HOSCF_ACC(14);
             if (j == 0) HOSCF_MARK(4);
             if (j == 1) HOSCF_MARK(6);
         }
@@ -615,7 +654,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
 
     if (!done && proj) {
         // mu = rb V_m t, t solving (T_m - shift/(N-1)) t = e_1
-        own_combine(V, D, m, r_lo, r_hi, L.s, L.part, w, false);
+        own_combine(ov, m, r_lo, r_hi, L.s, L.part, w, false);
         for (int64_t r = r_lo + tid; r < r_hi; r += BS) a.out[r] = (L.ok ? rb : 0.0) * w[r];
         if (blockIdx.x == 0 && tid == 0) {
             a.st->lanczos = m;
@@ -654,7 +693,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     if (accept) {
         // y = V_m s (own rows), then per-block norm and largest-|entry|
         const int N = a.N;
-        own_combine(V, D, m, r_lo, r_hi, L.s, L.part, w, false);
+        own_combine(ov, m, r_lo, r_hi, L.s, L.part, w, false);
         __shared__ double wbv[BS / 64], wbs[BS / 64];
         __shared__ int64_t wbi[BS / 64];
         for (int n = 0; n < N; ++n) {
@@ -718,12 +757,21 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             parity ^= 1;
             for (int k = tid; k < 4 * N; k += BS) st_ag(buf + (size_t)blockIdx.x * a.RK + k, L.mine[k]);
             flag_barrier(a, ++sync, &L.timeout);
+            // gather every workgroup's 4N values into LDS with all threads
+            // (independent loads in flight), then combine in workgroup order
+            double* stage = vlds;
+            const int K4 = 4 * N;
+            for (int idx = tid; idx < a.nwg * K4; idx += BS) {
+                const int wg = idx / K4, k = idx - wg * K4;
+                stage[idx] = ld_ag(buf + (size_t)wg * a.RK + k);
+            }
+            __syncthreads();
             if (tid == 0) {
                 for (int n = 0; n < N; ++n) {
                     double sn = 0.0, v = -1.0, sg = 0.0, ix = 1e300;
                     for (int wg = 0; wg < a.nwg; ++wg) {
-                        const double* p = buf + (size_t)wg * a.RK + 4 * n;
-                        const double p0 = ld_ag(p), p1 = ld_ag(p + 1), p2 = ld_ag(p + 2), p3 = ld_ag(p + 3);
+                        const double* p = stage + wg * K4 + 4 * n;
+                        const double p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
                         sn += p0;
                         if (p1 > v || (p1 == v && p2 < ix)) {
                             v = p1;
@@ -774,6 +822,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     HOSCF_MARK(8);
     if (tr) trace[9] = (uint64_t)m;
 #undef HOSCF_MARK
+#undef HOSCF_ACC
 }
 
 // ---------------------------------------------------------------------------
@@ -805,9 +854,12 @@ bool PostPlan::build(const BlockMap& map, bool f64_blocks, int kmax, int max_wg,
         }
     a.kmax = std::max(1, std::min<int>(kmax, std::min<int64_t>(kKmaxLds - 1, map.D)));
     const size_t esz = f64_blocks ? 8 : 4;
+    // Workgroups: about 64 KB of J (blocks and transposes) each, so that a
+    // J product is a few rows per wave; at most 64 (barrier and gather costs
+    // grow with the count) and at least 8 rows each.
     const double jbytes = 2.0 * (double)map.total() * (double)esz;
-    int nwg = (int)std::ceil(jbytes / (256.0 * 1024.0));
-    nwg = std::max(1, std::min<int>(nwg, (int)std::max<int64_t>(1, map.D / 32)));
+    int nwg = (int)std::ceil(jbytes / (64.0 * 1024.0));
+    nwg = std::max(1, std::min<int>(nwg, (int)std::max<int64_t>(1, map.D / 8)));
     nwg = std::min(nwg, std::max(1, std::min(max_wg, 64)));
     a.nwg = nwg;
     a.RK = kKmaxLds + 4 * kMaxOrder + 8;
