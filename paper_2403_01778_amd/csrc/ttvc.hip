@@ -28,6 +28,7 @@ namespace hoscf {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
 // Storage formats: load VEC consecutive elements (16 bytes when VEC > 1) and
@@ -43,20 +44,6 @@ template <> struct Fmt<HOSCF_FP8E4M3> { using S = uint8_t; using A = float; stat
 __device__ __forceinline__ float bf16_lo(unsigned u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16_hi(unsigned u) { return __uint_as_float(u & 0xffff0000u); }
 
-// OCP E4M3 -> f32 without tables: placing the 7 magnitude bits at bit 20 of a
-// binary32 pattern gives exponent field E and mantissa m/8 (normals) or the
-// denormal m * 2^-129 (E = 0); multiplying by 2^120 rebiases (7 -> 127)
-// exactly in both cases.
-__device__ __forceinline__ float e4m3_at(unsigned byte_bits_sign31, unsigned mag_at20) {
-    return __uint_as_float(byte_bits_sign31 | mag_at20) * 0x1p120f;
-}
-__device__ __forceinline__ void e4m3x4(unsigned u, float* o) {
-    o[0] = e4m3_at((u & 0x80u) << 24, (u & 0x7fu) << 20);
-    o[1] = e4m3_at((u & 0x8000u) << 16, (u & 0x7f00u) << 12);
-    o[2] = e4m3_at((u & 0x800000u) << 8, (u & 0x7f0000u) << 4);
-    o[3] = e4m3_at(u & 0x80000000u, (u & 0x7f000000u) >> 4);
-}
-
 template <int FMT, int V> struct Loader;
 
 template <int FMT> struct Loader<FMT, 1> {
@@ -67,10 +54,8 @@ template <int FMT> struct Loader<FMT, 1> {
     __device__ static Raw load(const S* p) { return __builtin_nontemporal_load(p); }
     __device__ static void cvt(Raw r, A* o) {
         if constexpr (FMT == HOSCF_BF16) o[0] = __uint_as_float(unsigned(r) << 16);
-        else if constexpr (FMT == HOSCF_FP8E4M3) {
-            unsigned u = r;
-            o[0] = e4m3_at((u & 0x80u) << 24, (u & 0x7fu) << 20);
-        } else o[0] = A(r);
+        else if constexpr (FMT == HOSCF_FP8E4M3) o[0] = __builtin_amdgcn_cvt_f32_fp8((int)(unsigned)r, 0);
+        else o[0] = A(r);
     }
 };
 
@@ -98,13 +83,21 @@ template <> struct Loader<HOSCF_BF16, 8> {
         o[4] = bf16_lo(r.z); o[5] = bf16_hi(r.z); o[6] = bf16_lo(r.w); o[7] = bf16_hi(r.w);
     }
 };
+// gfx950 converts OCP E4M3 in hardware, two codes per instruction (the word
+// select picks bytes 0-1 or 2-3); this keeps the FP8 sweep bound by HBM
+// rather than by the decode arithmetic.
+__device__ __forceinline__ void e4m3x4_hw(unsigned u, float* o) {
+    const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, false);
+    const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, true);
+    o[0] = lo.x; o[1] = lo.y; o[2] = hi.x; o[3] = hi.y;
+}
 template <> struct Loader<HOSCF_FP8E4M3, 16> {
     using A = float;
     using Raw = u32x4;
     __device__ static Raw zero() { return Raw{0u, 0u, 0u, 0u}; }
     __device__ static Raw load(const uint8_t* p) { return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)); }
     __device__ static void cvt(Raw r, A* o) {
-        e4m3x4(r.x, o); e4m3x4(r.y, o + 4); e4m3x4(r.z, o + 8); e4m3x4(r.w, o + 12);
+        e4m3x4_hw(r.x, o); e4m3x4_hw(r.y, o + 4); e4m3x4_hw(r.z, o + 8); e4m3x4_hw(r.w, o + 12);
     }
 };
 

@@ -98,3 +98,48 @@ def test_tune_table_validation(lib):
     with pytest.raises(lib.HoscfError):
         lib.tune_set(7, dims, (0, 1, 32, 1, 8, 8))
     lib.tune_clear()
+
+
+def test_batch_plan_rejects_bad_descriptors(lib):
+    """hoscf_batch_plan_create validates every descriptor and option on the
+    host before it touches the device."""
+    so = lib._lib
+
+    def create(descs, R, opts=None):
+        arr = (lib.HoscfTensor * len(descs))(*descs)
+        h = ctypes.c_void_p()
+        o = opts if opts is not None else lib.options(algo="hoscf", tol=1e-6)
+        return so.hoscf_batch_plan_create(len(descs), arr, R, ctypes.byref(o), ctypes.byref(h)), h
+
+    ok = _desc(lib, [8, 9, 10])
+    assert create([ok, _desc(lib, [8, 9])], 2)[0] == lib.INVALID_ARG           # order 2
+    assert create([ok, _desc(lib, [8, 97, 10])], 2)[0] == lib.INVALID_ARG      # dim > 96
+    assert create([ok, _desc(lib, [8, 9, 10], dtype=0)], 2)[0] == lib.INVALID_ARG  # FP64 storage
+    assert create([ok, _desc(lib, [8, 9, 10], data=0)], 2)[0] == lib.INVALID_ARG   # null data
+    assert create([ok], 0)[0] == lib.INVALID_ARG                                # R < 1
+    assert create([ok], 17)[0] == lib.INVALID_ARG                               # R > 16
+    assert create([ok], 2, lib.options(algo="ihoscf"))[0] == lib.INVALID_ARG   # HOSCF only
+    assert create([ok], 2, lib.options(algo="hoscf", inner_rel=-1.0))[0] == lib.INVALID_ARG
+    # an empty batch is a valid no-op plan
+    rc, h = create([], 2)
+    if rc == lib.OK:
+        assert so.hoscf_batch_workspace_size(h) >= 0
+        so.hoscf_plan_destroy(h)
+
+
+def test_backward_argument_checks(lib):
+    so = lib._lib
+    good = _desc(lib, [4, 5, 6])
+    # null x / grad, bad grad dtype, non-finite sigma: rejected before any launch
+    assert so.hoscf_backward(ctypes.byref(good), None, 1.0, 1.0, None, 0x10, lib.F32, None, None, 0x10, 1 << 30,
+                             None) == lib.INVALID_ARG
+    assert so.hoscf_backward(ctypes.byref(good), 0x10, 1.0, 1.0, None, None, lib.F32, None, None, 0x10, 1 << 30,
+                             None) == lib.INVALID_ARG
+    assert so.hoscf_backward(ctypes.byref(good), 0x10, 1.0, 1.0, None, 0x10, lib.BF16, None, None, 0x10, 1 << 30,
+                             None) == lib.INVALID_ARG
+    assert so.hoscf_backward(ctypes.byref(good), 0x10, float("nan"), 1.0, None, 0x10, lib.F32, None, None, 0x10,
+                             1 << 30, None) == lib.INVALID_ARG
+    assert so.hoscf_ttvc_backward(ctypes.byref(good), 0x10, None, None, float("inf"), 0x10, lib.F32, None, 0x10,
+                                  1 << 30, None) == lib.INVALID_ARG
+    assert so.hoscf_backward(ctypes.byref(good), 0x10, 1.0, 1.0, None, 0x10, lib.F32, None, None, 0x10, 8,
+                             None) == lib.WORKSPACE_TOO_SMALL
