@@ -26,6 +26,8 @@ namespace hoscf {
 constexpr int kBatchMaxDim = 96;
 constexpr int kBatchMaxD = 3 * kBatchMaxDim;
 constexpr int kBatchKmax = 64;  // Lanczos steps per eigen-step
+constexpr int kBatchMaxR = 8;   // rank-one terms per tensor (registers hold the earlier terms' entries)
+constexpr int kBatchThreads = 256;
 
 struct BatchItem {
     const float* T;
@@ -47,6 +49,10 @@ struct BatchArgs {
     int32_t* iters_out;
     double* scratch;     // [grid][(kBatchKmax + 1) * kBatchMaxD]
     unsigned* counter;   // work queue head
+    // workgroup 0's time per phase (100 MHz clock), summed over its terms:
+    // [0] deflation set-up, [1] sweep, [2] epilogue, [3] J products,
+    // [4] reorthogonalisation, [5] checks, [6] new vector, [7] normalisation
+    unsigned long long* prof;
 };
 
 // LDS layout (bytes): blocks A12 | A13 | A23 (FP32, sized for the largest
@@ -84,6 +90,21 @@ __device__ double block_sum(double v, double* red) {
     return t;
 }
 
+// sum_t a[t * stride] * v[t] for t < n in FP64, four independent partial
+// sums (t mod 4) so consecutive FMAs do not wait on each other.
+__device__ __forceinline__ double dot4(const float* a, int stride, const double* v, int n) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int t = 0;
+    for (; t + 3 < n; t += 4) {
+        s0 = fma((double)a[t * stride], v[t], s0);
+        s1 = fma((double)a[(t + 1) * stride], v[t + 1], s1);
+        s2 = fma((double)a[(t + 2) * stride], v[t + 2], s2);
+        s3 = fma((double)a[(t + 3) * stride], v[t + 3], s3);
+    }
+    for (; t < n; ++t) s0 = fma((double)a[t * stride], v[t], s0);
+    return (s0 + s1) + (s2 + s3);
+}
+
 // out = (N-1) J v = M v for the three blocks (rows split over threads);
 // v and out are FP64 vectors in LDS, in the stacked [u1; u2; u3] layout.
 __device__ void bmatvec(const BatchLds& L, const int* I, const double* v, double* out, int BT) {
@@ -93,31 +114,173 @@ __device__ void bmatvec(const BatchLds& L, const int* I, const double* v, double
     const float* A23 = A13 + I1 * I3;
     const int D = I1 + I2 + I3;
     for (int r = threadIdx.x; r < D; r += BT) {
-        double acc = 0.0;
+        double acc;
         if (r < I1) {
             const int i = r;
-            for (int j = 0; j < I2; ++j) acc = fma((double)A12[i * I2 + j], v[I1 + j], acc);
-            for (int k = 0; k < I3; ++k) acc = fma((double)A13[i * I3 + k], v[I1 + I2 + k], acc);
+            acc = dot4(A12 + i * I2, 1, v + I1, I2) + dot4(A13 + i * I3, 1, v + I1 + I2, I3);
         } else if (r < I1 + I2) {
             const int j = r - I1;
-            for (int i = 0; i < I1; ++i) acc = fma((double)A12[i * I2 + j], v[i], acc);
-            for (int k = 0; k < I3; ++k) acc = fma((double)A23[j * I3 + k], v[I1 + I2 + k], acc);
+            acc = dot4(A12 + j, I2, v, I1) + dot4(A23 + j * I3, 1, v + I1 + I2, I3);
         } else {
             const int k = r - I1 - I2;
-            for (int i = 0; i < I1; ++i) acc = fma((double)A13[i * I3 + k], v[i], acc);
-            for (int j = 0; j < I2; ++j) acc = fma((double)A23[j * I3 + k], v[I1 + j], acc);
+            acc = dot4(A13 + k, I3, v, I1) + dot4(A23 + k, I3, v + I1, I2);
         }
         out[r] = acc;
     }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int VEC> struct SlabVec;
+template <> struct SlabVec<1> { typedef float T; };
+template <> struct SlabVec<4> { typedef f32x4 T; };
+
+// The three blocks of one tensor at the factors in L.u, deflated by the
+// earlier terms (coefficients in L.defl), written to LDS in FP32; returns the
+// thread's share of sum ||A||^2.  Slabs T[i,:,:] are read as VEC-float
+// vectors; slab i is staged in LDS while slabs i+1 and i+2 are in flight in
+// registers (three buffers, so two slabs of latency are hidden behind the
+// row sums of the current one).  Loads are unconditional (clamped slab
+// index past the end) so the compiler always knows how many are in flight.
+template <int BT, int VEC>
+__device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& item, int r, int D) {
+    using LT = typename SlabVec<VEC>::T;
+    constexpr int QV = (kSlabFloats / VEC + BT - 1) / BT;
+    constexpr int RMAX = kBatchMaxR;
+    const int tid = threadIdx.x;
+    const int I1 = item.I[0], I2 = item.I[1], I3 = item.I[2];
+    const int n23 = I2 * I3, nv = n23 / VEC;
+    float* A12 = L.blk;
+    float* A13 = A12 + I1 * I2;
+    float* A23 = A13 + I1 * I3;
+    const LT* Tv = reinterpret_cast<const LT*>(item.T);
+    // deflation: row threads keep their fixed factor entries of the earlier
+    // terms (x_{s,2}[j] for A12 rows, x_{s,3}[k] for A13 rows) and thread t
+    // keeps x_{s,1}[t], published to LDS when slab t is processed
+    double cfix[RMAX], x1r[RMAX];
+    {
+        const int col = tid < I2 ? I1 + tid : (tid >= BT / 2 && tid < BT / 2 + I3 ? I1 + I2 + tid - BT / 2 : -1);
+#pragma unroll
+        for (int s2 = 0; s2 < RMAX; ++s2) {
+            const double* xs = a.x_out + item.xoff + (int64_t)s2 * D;
+            cfix[s2] = (s2 < r && col >= 0) ? xs[col] : 0.0;
+            x1r[s2] = (s2 < r && tid < I1) ? xs[tid] : 0.0;
+        }
+    }
+    double acc[QV][VEC];
+#pragma unroll
+    for (int q = 0; q < QV; ++q)
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) acc[q][c] = 0.0;
+    LT b0[QV], b1[QV], b2[QV];
+    double fro = 0.0;
+    // The slab step is written out for each buffer rotation (a macro rather
+    // than a function taking the buffers by pointer, so that the buffers stay
+    // in registers).
+#define BATCH_LOAD(B, I)                                      \
+    {                                                         \
+        const LT* S_ = Tv + (int64_t)(I) * nv;                 \
+        _Pragma("unroll") for (int q = 0; q < QV; ++q) {      \
+            const int e = tid + q * BT;                       \
+            B[q] = S_[e < nv ? e : 0];                        \
+        }                                                     \
+    }
+#define BATCH_STEP(CUR, LD, I)                                                                   \
+    {                                                                                            \
+        const int i_ = (I);                                                                      \
+        const bool live = i_ < I1;                                                               \
+        if (live) {                                                                              \
+            _Pragma("unroll") for (int q = 0; q < QV; ++q) {                                     \
+                const int e = tid + q * BT;                                                      \
+                if (e < nv) *reinterpret_cast<LT*>(L.a.slab + e * VEC) = CUR[q];                 \
+            }                                                                                    \
+            if (tid == i_)                                                                       \
+                _Pragma("unroll") for (int s2 = 0; s2 < RMAX; ++s2) if (s2 < r) L.xi[s2] = x1r[s2]; \
+        }                                                                                        \
+        BATCH_LOAD(LD, i_ + 2 < I1 ? i_ + 2 : I1 - 1)                                             \
+        __syncthreads();                                                                         \
+        if (live) slab_rows(CUR, i_);                                                            \
+        __syncthreads();                                                                         \
+    }
+    auto slab_rows = [&](const LT* cur, int i) {
+        const double u1i = L.u[i];
+#pragma unroll
+        for (int q = 0; q < QV; ++q) {
+            if constexpr (VEC == 1) {
+                acc[q][0] = fma((double)cur[q], u1i, acc[q][0]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < VEC; ++c) acc[q][c] = fma((double)cur[q][c], u1i, acc[q][c]);
+            }
+        }
+        // row i of A12 (threads 0..I2-1) and of A13 (threads BT/2..BT/2+I3-1)
+        if (tid < I2) {
+            const int j = tid;
+            const double s = dot4(L.a.slab + j * I3, 1, L.u + I1 + I2, I3);
+            double corr = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < RMAX; ++s2)
+                if (s2 < r) corr = fma(L.defl[3 * s2 + 0] * L.xi[s2], cfix[s2], corr);
+            const float v = (float)(s - corr);
+            A12[i * I2 + j] = v;
+            fro = fma((double)v, (double)v, fro);
+        } else if (tid >= BT / 2 && tid < BT / 2 + I3) {
+            const int k = tid - BT / 2;
+            const double s = dot4(L.a.slab + k, I3, L.u + I1, I2);
+            double corr = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < RMAX; ++s2)
+                if (s2 < r) corr = fma(L.defl[3 * s2 + 1] * L.xi[s2], cfix[s2], corr);
+            const float v = (float)(s - corr);
+            A13[i * I3 + k] = v;
+            fro = fma((double)v, (double)v, fro);
+        }
+    };
+    BATCH_LOAD(b0, 0)
+    BATCH_LOAD(b1, I1 > 1 ? 1 : 0)
+    for (int i = 0; i < I1; i += 3) {
+        BATCH_STEP(b0, b2, i)
+        BATCH_STEP(b1, b0, i + 1)
+        BATCH_STEP(b2, b1, i + 2)
+    }
+#undef BATCH_STEP
+#undef BATCH_LOAD
+    // block (2,3): the register accumulators, deflated, rounded once
+#pragma unroll
+    for (int q = 0; q < QV; ++q) {
+        const int e = tid + q * BT;
+        if (e < nv) {
+#pragma unroll
+            for (int c = 0; c < VEC; ++c) {
+                const int f = e * VEC + c;
+                const int j = f / I3, k = f - j * I3;
+                double corr = 0.0;
+                for (int s2 = 0; s2 < r; ++s2) {
+                    const double* xs = a.x_out + item.xoff + (int64_t)s2 * D;
+                    corr = fma(L.defl[3 * s2 + 2] * xs[I1 + j], xs[I1 + I2 + k], corr);
+                }
+                const float v = (float)(acc[q][c] - corr);
+                A23[f] = v;
+                fro = fma((double)v, (double)v, fro);
+            }
+        }
+    }
+    return fro;
 }
 
 template <int BT>
 __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BatchLds& L = *reinterpret_cast<BatchLds*>(lds_raw);
-    constexpr int QM = (kSlabFloats + BT - 1) / BT;  // slab elements per thread
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double* V = a.scratch + (size_t)blockIdx.x * (kBatchKmax + 1) * kBatchMaxD;
+    const bool tr = blockIdx.x == 0 && tid == 0;
+    unsigned long long tprev = tr ? __builtin_amdgcn_s_memrealtime() : 0ull;
+#define BATCH_ACC(k)                                                   \
+    if (tr) {                                                          \
+        const unsigned long long now_ = __builtin_amdgcn_s_memrealtime(); \
+        a.prof[k] += now_ - tprev;                                     \
+        tprev = now_;                                                  \
+    }
 
     for (;;) {
         if (tid == 0) L.item = (int)atomicAdd(a.counter, 1u);
@@ -175,93 +338,13 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                 }
                 for (int q = tid; q < D; q += BT) L.uf[q] = (float)L.u[q];
                 __syncthreads();
+                BATCH_ACC(0);
 
                 // ---- sweep: blocks at u, FP64 accumulation ----
-                double acc23[QM];
-                float cur[QM], nxt[QM];
-#pragma unroll
-                for (int q = 0; q < QM; ++q) {
-                    acc23[q] = 0.0;
-                    const int e = tid + q * BT;
-                    cur[q] = item.T[e < n23 ? e : 0];
-                }
-                // deflation: the row threads keep their fixed factor entries of the
-                // previous terms in registers (x_{s,2}[j] for A12 rows, x_{s,3}[k]
-                // for A13 rows); the mode-1 entries x_{s,1}[i] of the current slab
-                // are staged in LDS with the slab
-                constexpr int RMAX = 16;
-                double cfix[RMAX];
-                {
-                    const int col = tid < I2 ? I1 + tid : (tid >= BT / 2 && tid < BT / 2 + I3 ? I1 + I2 + tid - BT / 2 : -1);
-#pragma unroll
-                    for (int s2 = 0; s2 < RMAX; ++s2) {
-                        const double* xs = a.x_out + item.xoff + (int64_t)s2 * D;
-                        cfix[s2] = (s2 < r && col >= 0) ? xs[col] : 0.0;
-                    }
-                }
-                double fro = 0.0;
-                for (int i = 0; i < I1; ++i) {
-#pragma unroll
-                    for (int q = 0; q < QM; ++q) {
-                        const int e = tid + q * BT;
-                        if (e < n23) L.a.slab[e] = cur[q];
-                    }
-                    if (tid < r) L.xi[tid] = a.x_out[item.xoff + (int64_t)tid * D + i];
-                    const int inext = i + 1 < I1 ? i + 1 : i;
-                    const float* Tn = item.T + (int64_t)inext * n23;
-#pragma unroll
-                    for (int q = 0; q < QM; ++q) {
-                        const int e = tid + q * BT;
-                        nxt[q] = Tn[e < n23 ? e : 0];
-                    }
-                    __syncthreads();
-                    const double u1i = L.u[i];
-#pragma unroll
-                    for (int q = 0; q < QM; ++q) acc23[q] = fma((double)cur[q], u1i, acc23[q]);
-                    // row i of A12 (threads 0..I2-1) and of A13 (threads BT/2..BT/2+I3-1)
-                    if (tid < I2) {
-                        const int j = tid;
-                        double acc = 0.0;
-                        for (int k = 0; k < I3; ++k) acc = fma((double)L.a.slab[j * I3 + k], L.u[I1 + I2 + k], acc);
-                        double corr = 0.0;
-#pragma unroll
-                        for (int s2 = 0; s2 < RMAX; ++s2)
-                            if (s2 < r) corr = fma(L.defl[3 * s2 + 0] * L.xi[s2], cfix[s2], corr);
-                        const float v = (float)(acc - corr);
-                        A12[i * I2 + j] = v;
-                        fro = fma((double)v, (double)v, fro);
-                    } else if (tid >= BT / 2 && tid < BT / 2 + I3) {
-                        const int k = tid - BT / 2;
-                        double acc = 0.0;
-                        for (int j = 0; j < I2; ++j) acc = fma((double)L.a.slab[j * I3 + k], L.u[I1 + j], acc);
-                        double corr = 0.0;
-#pragma unroll
-                        for (int s2 = 0; s2 < RMAX; ++s2)
-                            if (s2 < r) corr = fma(L.defl[3 * s2 + 1] * L.xi[s2], cfix[s2], corr);
-                        const float v = (float)(acc - corr);
-                        A13[i * I3 + k] = v;
-                        fro = fma((double)v, (double)v, fro);
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int q = 0; q < QM; ++q) cur[q] = nxt[q];
-                }
-#pragma unroll
-                for (int q = 0; q < QM; ++q) {
-                    const int e = tid + q * BT;
-                    if (e < n23) {
-                        const int j = e / I3, k = e - j * I3;
-                        double corr = 0.0;
-                        for (int s = 0; s < r; ++s) {
-                            const double* xs = a.x_out + item.xoff + (int64_t)s * D;
-                            corr = fma(L.defl[3 * s + 2] * xs[I1 + j], xs[I1 + I2 + k], corr);
-                        }
-                        const float v = (float)(acc23[q] - corr);
-                        A23[e] = v;
-                        fro = fma((double)v, (double)v, fro);
-                    }
-                }
+                const bool vec_ok = (n23 % 4) == 0 && (reinterpret_cast<uintptr_t>(item.T) & 15) == 0;
+                double fro = vec_ok ? batch_sweep<BT, 4>(a, L, item, r, D) : batch_sweep<BT, 1>(a, L, item, r, D);
                 fro = block_sum<BT>(fro, L.red);  // includes the barrier after the block writes
+                BATCH_ACC(1);
 
                 // ---- g = M u / 2, sigma, ||J||_F, residual ----
                 bmatvec(L, I, L.u, L.g, BT);
@@ -292,6 +375,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                     status = HOSCF_OK;
                     break;
                 }
+                BATCH_ACC(2);
                 if (iters >= a.max_iter) break;
                 ++iters;
 
@@ -313,6 +397,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                     __syncthreads();
                     for (int q = tid; q < D; q += BT) w[q] *= 0.5;
                     __syncthreads();
+                    BATCH_ACC(3);
                     // two passes of classical Gram-Schmidt against V_0..V_j
                     for (int pass = 0; pass < 2; ++pass) {
                         for (int i0 = wave; i0 <= j; i0 += BT / 64) {
@@ -340,8 +425,9 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                     }
                     __syncthreads();
                     m = j + 1;
+                    BATCH_ACC(4);
                     const bool invariant = beta <= 1e-14 * normJ;
-                    if (invariant || m == kBatchKmax || m <= 8 || (m % 4) == 0) {
+                    if (invariant || m == kBatchKmax || (m >= 3 && (m <= 8 || (m % 4) == 0))) {
                         if (tid < 64) {
                             double lmin = L.al[0], lmax = L.al[0];
                             if (m > 1) extreme_eigs(L.al, L.b2, L.be, m, &lmin, &lmax);
@@ -365,6 +451,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                         stop = L.stop != 0;
                         __syncthreads();
                     }
+                    BATCH_ACC(5);
                     if (!stop) {
                         const double ib = 1.0 / beta;
                         double* Vn = V + (size_t)(j + 1) * kBatchMaxD;
@@ -376,6 +463,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                         __syncthreads();
                     }
                 }
+                BATCH_ACC(6);
                 // y = V_m s, block norms and largest-|entry| signs
                 double* y = w;
                 for (int q = tid; q < D; q += BT) {
@@ -417,6 +505,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                     L.u[q] = y[q] * L.sc[n];
                 }
                 __syncthreads();
+                BATCH_ACC(7);
             }
             // final sign fix: sigma >= 0 via u_1
             const bool flip = sigma < 0.0;
@@ -433,8 +522,11 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
     }
 }
 
-__global__ void batch_reset_kernel(unsigned* counter) {
+#undef BATCH_ACC
+
+__global__ void batch_reset_kernel(unsigned* counter, unsigned long long* prof) {
     if (threadIdx.x == 0) *counter = 0u;
+    if (threadIdx.x < 8) prof[threadIdx.x] = 0ull;
 }
 
 }  // namespace hoscf
@@ -446,7 +538,7 @@ struct hoscf_plan {
     hoscf_options opts{};
     BatchItem* items = nullptr;  // device, largest first
     int grid = 0;
-    int bt = 256;
+    int bt = kBatchThreads;
     size_t ws_bytes = 0;
 };
 
@@ -476,7 +568,7 @@ int hoscf_batch_plan_create(int B, const hoscf_tensor* descs, int R, const hoscf
                             hoscf_plan** out) {
     if (!out) return HOSCF_INVALID_ARG;
     *out = nullptr;
-    if (B < 0 || R < 1 || R > 16 || (B > 0 && !descs)) return HOSCF_INVALID_ARG;
+    if (B < 0 || R < 1 || R > kBatchMaxR || (B > 0 && !descs)) return HOSCF_INVALID_ARG;
     hoscf_options o{};
     o.algo = 0;
     o.tol = 1e-6;
@@ -508,8 +600,8 @@ int hoscf_batch_plan_create(int B, const hoscf_tensor* descs, int R, const hoscf
     p->B = B;
     p->R = R;
     p->opts = o;
-    p->bt = 256;
-    p->grid = batch_grid<256>();
+    p->bt = kBatchThreads;
+    p->grid = batch_grid<kBatchThreads>();
     if (p->grid <= 0) {
         delete p;
         return HOSCF_HIP_ERROR;
@@ -557,9 +649,10 @@ int hoscf_solve_batched(const hoscf_plan* plan, const double* x0, double* x_out,
     a.status_out = status_out;
     a.iters_out = iters_out;
     a.counter = static_cast<unsigned*>(ws);
+    a.prof = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + 64);
     a.scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + 256);
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, a.counter);
-    hipLaunchKernelGGL(batch_kernel<256>, dim3((unsigned)plan->grid), dim3(256), kLdsBytes, s, a);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, a.counter, a.prof);
+    hipLaunchKernelGGL(batch_kernel<kBatchThreads>, dim3((unsigned)plan->grid), dim3(kBatchThreads), kLdsBytes, s, a);
     return hipGetLastError() == hipSuccess ? HOSCF_OK : HOSCF_HIP_ERROR;
 }
 

@@ -556,31 +556,56 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 if (j == 1) HOSCF_MARK(5);
             }
             HOSCF_ACC(10);
-            // pass 1: h_i = V_i . w over own rows
+            // pass 1: h_i = V_i . w over own rows, with ||w||^2 in the same
+            // reduction
             own_dots(ov, w, j, r_lo, r_hi, L.mine);
             if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 1, L);
-            allreduce(a, j + 1 + NP, parity, sync, L, vlds);
+            {
+                double nn0 = 0.0;
+                for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn0 = fma(w[r], w[r], nn0);
+                nn0 = wg_sum(nn0, L.red4);
+                if (tid == 0) L.mine[j + 1 + NP] = nn0;
+            }
+            allreduce(a, j + 2 + NP, parity, sync, L, vlds);
             own_combine(ov, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
             if (proj) own_xsub(a, w, L.hsum + j + 1, r_lo, r_hi, L);
-            if (tid == 0) L.al[j] = L.hsum[j];
-            __syncthreads();
-            HOSCF_ACC(11);
-            // pass 2: h'_i and ||w||^2
-            own_dots(ov, w, j, r_lo, r_hi, L.mine);
-            double nn = 0.0;
-            for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
-            nn = wg_sum(nn, L.red4);
-            if (tid == 0) L.mine[j + 1] = nn;
-            if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 2, L);
-            allreduce(a, j + 2 + NP, parity, sync, L, vlds);
-            double corr2 = 0.0;
-            for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
-            for (int i = 0; i < NP; ++i) corr2 = fma(L.hsum[j + 2 + i], L.hsum[j + 2 + i], corr2);
-            const double beta = sqrt(fmax(L.hsum[j + 1] - corr2, 0.0));
-            own_combine(ov, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
-            if (proj) own_xsub(a, w, L.hsum + j + 2, r_lo, r_hi, L);
+            // The second pass is needed only when the first removed most of w
+            // (Kahan / DGKS: the orthogonalised norm, known from Pythagoras,
+            // is below 1/sqrt(2) of the original); every workgroup decides
+            // alike from the same reduced numbers.
+            double beta;
+            {
+                double c1 = 0.0;
+                for (int i = 0; i < j + 1 + NP; ++i) c1 = fma(L.hsum[i], L.hsum[i], c1);
+                const double before2 = L.hsum[j + 1 + NP];
+                const double after2 = before2 - c1;
+                const double alpha1 = L.hsum[j];
+                __syncthreads();
+                HOSCF_ACC(11);
+                if (after2 >= 0.5 * before2) {
+                    beta = sqrt(fmax(after2, 0.0));
+                    if (tid == 0) L.al[j] = alpha1;
+                } else {
+                    if (tid == 0) L.al[j] = alpha1;
+                    __syncthreads();
+                    // pass 2: h'_i and ||w||^2
+                    own_dots(ov, w, j, r_lo, r_hi, L.mine);
+                    double nn = 0.0;
+                    for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
+                    nn = wg_sum(nn, L.red4);
+                    if (tid == 0) L.mine[j + 1] = nn;
+                    if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 2, L);
+                    allreduce(a, j + 2 + NP, parity, sync, L, vlds);
+                    double corr2 = 0.0;
+                    for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
+                    for (int i = 0; i < NP; ++i) corr2 = fma(L.hsum[j + 2 + i], L.hsum[j + 2 + i], corr2);
+                    beta = sqrt(fmax(L.hsum[j + 1] - corr2, 0.0));
+                    own_combine(ov, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
+                    if (proj) own_xsub(a, w, L.hsum + j + 2, r_lo, r_hi, L);
+                    if (tid == 0) L.al[j] += L.hsum[j];
+                }
+            }
             if (tid == 0) {
-                L.al[j] += L.hsum[j];
                 L.be[j] = beta;
                 L.b2[j] = beta * beta;
             }
@@ -589,7 +614,10 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             m = j + 1;
             rho = proj ? a.shift * inv_n1 : L.al[0];
             const bool invariant = beta <= 1e-14 * normJ;
-            const bool check = invariant || m == kmax || m <= 8 || (m % 4) == 0;
+            // an eigen-step almost never converges in one or two Lanczos steps
+            // (and a Galerkin solve needs two); checks cost a serial
+            // tridiagonal eigensolve, so they start at m = 3
+            const bool check = invariant || m == kmax || (m >= 3 && (m <= 8 || (m % 4) == 0));
             if (check) {
                 // every workgroup takes the same decision from the same numbers
                 if (a.mode == kPostEigen) {

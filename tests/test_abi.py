@@ -117,7 +117,7 @@ def test_batch_plan_rejects_bad_descriptors(lib):
     assert create([ok, _desc(lib, [8, 9, 10], dtype=0)], 2)[0] == lib.INVALID_ARG  # FP64 storage
     assert create([ok, _desc(lib, [8, 9, 10], data=0)], 2)[0] == lib.INVALID_ARG   # null data
     assert create([ok], 0)[0] == lib.INVALID_ARG                                # R < 1
-    assert create([ok], 17)[0] == lib.INVALID_ARG                               # R > 16
+    assert create([ok], 9)[0] == lib.INVALID_ARG                                # R > 8
     assert create([ok], 2, lib.options(algo="ihoscf"))[0] == lib.INVALID_ARG   # HOSCF only
     assert create([ok], 2, lib.options(algo="hoscf", inner_rel=-1.0))[0] == lib.INVALID_ARG
     # an empty batch is a valid no-op plan
