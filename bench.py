@@ -6,13 +6,24 @@ sweeps, FP64 eigen-steps, normalisation and signs, the stopping test, the final
 sign fix): order-3 800 x 800 x 800 FP32 tensor (2.048 GB), N(0,1) noise plus a
 planted rank-one term with lambda = 3 sqrt(prod I)/sqrt(max I) = 2400 and unit
 Gaussian factors, seeded (seed 2); seeded Gaussian unit initial factors; plain
-HOSCF, tol 1e-6.  The input is resident in HBM before the timed region.
+HOSCF (exact inner eigen-steps), tol 1e-6.  The input is resident in HBM
+before the timed region.
 
-Printed: one JSON line.  `value` is whole-job TTVc throughput: bytes of T
-streamed by all sweeps of the timed solves divided by their wall time (so the
-eigen-steps and host round trips count against it).  `roofline` is the level-1
-TTVc kernel alone, timed with HIP events on its own stream.  `cpu_baseline` is
-the FP64 oracle on the host cores over a bounded sample of the same workload.
+Printed: one JSON line.
+  value         whole-job TTVc throughput: bytes of T streamed by all sweeps of
+                the timed solves / their wall time (eigen-steps and host round
+                trips count against it).
+  chosen_vs_plain  the same workload under the solver variants (inexact inner
+                solves, iHOSCF), each with its sigma error against the FP64
+                oracle; "chosen" is the fastest with error <= 1e-6.
+  roofline      the level-1 TTVc kernel alone, timed with HIP events on its own
+                stream, against 8 TB/s; traffic = HBM bytes per launch from the
+                rocprofv3 counter passes (null once the kernel source differs
+                from the one they were taken on).
+  extras        the precision form (64^5, FP32 vs BF16 / FP8 storage), the
+                batched form (4096 tensors, rank 8, one launch) and the backward
+                pass (256^3 items).
+  cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
 """
 from __future__ import annotations
 
@@ -34,8 +45,8 @@ HBM_PEAK_GBPS = 8000.0
 # factors a 1 GiB device copy reads on the same counters); summary in
 # profiles/ttvc3_kernel_800cubed_f32_pmc.md.  Valid only for the kernel source
 # the counters were taken on.
-TRAFFIC = {"kernel_source_sha256": "0c235c976cd7ae24a70d1aabb0e41ac2435386733c34f06340fd852e85573f55",
-           "read_bytes": 2_000_217.8 * 1024, "write_bytes": 85_000.0 * 1024}
+TRAFFIC = {"kernel_source_sha256": "3d99058a09ecb3839984b0cdd02d03ffda4c0ab2b81f2ba80114fb0ee9266384",
+           "read_bytes": 2_000_220.4 * 1024, "write_bytes": 85_000.0 * 1024}
 
 
 def measured_traffic():

@@ -175,3 +175,33 @@ def test_inexact_inner_solves_same_point(lib, algo):
     assert info.status == 0
     assert_parity(T, x, sig, ref, 1e-12)
     assert info.lanczos_steps <= info_e.lanczos_steps
+
+
+def test_singleton_modes_closed_forms(lib):
+    """Modes of size 1 reduce the problem to closed forms: (1, I, J) is the
+    matrix case (sigma = top singular value of T[0]); (1, 1, K) is a vector
+    (sigma = ||T||, u_3 = T / ||T||)."""
+    rng = np.random.default_rng(71)
+    A = rng.standard_normal((1, 40, 30))
+    sig, x, info = gpu_solve(lib, A, synth.init_factors(A.shape, 71), "hoscf", 1e-12, 200)
+    assert info.status == 0
+    assert sig == pytest.approx(np.linalg.svd(A[0], compute_uv=False)[0], rel=1e-12)
+    v = rng.standard_normal((1, 1, 50))
+    sig, x, info = gpu_solve(lib, v, synth.init_factors(v.shape, 72), "hoscf", 1e-12, 10)
+    assert info.status == 0
+    assert sig == pytest.approx(np.linalg.norm(v), rel=1e-12)
+    u3 = oracle.split(x, v.shape)[2]
+    assert oracle.angle(u3, v.ravel()) <= 1e-10
+
+
+@pytest.mark.parametrize("algo", ["hoscf", "ihoscf"])
+def test_order8_fp64(lib, algo):
+    """The largest order the library takes (8), FP64, against the oracle."""
+    dims = (3, 4, 3, 2, 3, 4, 2, 3)
+    T, _ = synth.planted_rank_one(dims, synth.planted_lambda(dims), 81, dtype=np.float64)
+    x0 = synth.init_factors(dims, 81)
+    ref = oracle.hoscf(T, x0, algo=algo, tol=1e-11, max_iter=500)
+    assert ref.status == oracle.OK
+    sig, x, info = gpu_solve(lib, T, x0, algo, 1e-11, 500)
+    assert info.status == 0
+    assert_parity(T, x, sig, ref, 1e-12)

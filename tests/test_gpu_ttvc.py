@@ -55,7 +55,8 @@ def _check_against_oracle(lib, Tt, x, scale=1.0, Tstored=None):
 
 
 @pytest.mark.parametrize("dims", [(37, 29, 23), (130, 257, 300), (64, 64, 64), (3, 5, 7), (1, 1, 1), (2, 1, 3),
-                                  (10, 10, 7), (5, 300, 2), (257, 3, 1000)])
+                                  (10, 10, 7), (5, 300, 2), (257, 3, 1000), (90, 70, 801), (1, 50, 60),
+                                  (50, 60, 1), (600, 2, 2)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_ttvc_order3(lib, dims, dtype):
     Tt, x = _case(dims, dtype, 1000 + sum(dims))
