@@ -184,8 +184,13 @@ int hoscf_profile_sweep(const hoscf_tensor* T, const double* x, void* blocks, do
     if (!ws || !lay.build(*T, blocks, false, 1, ws, ws_bytes, tiling)) return HOSCF_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nn = std::max(1, lay.sweep.num_nodes());
-    std::vector<hipEvent_t> ev(2 * nn + 2);
-    for (auto& e : ev) HOSCF_TRY(hipEventCreate(&e));
+    std::vector<hipEvent_t> ev(2 * nn + 2, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return HOSCF_HIP_ERROR;
+        }
     double tot = 0.0, k1 = 0.0, k1root = 0.0;
     int rc = HOSCF_OK;
     for (int r = 0; r < reps && rc == HOSCF_OK; ++r) {

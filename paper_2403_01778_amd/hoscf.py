@@ -396,8 +396,9 @@ class BatchPlan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.hoscf_plan_destroy(h)
+        lib = globals().get("_lib")  # None while the interpreter shuts down
+        if h is not None and h.value and lib is not None:
+            lib.hoscf_plan_destroy(h)
             self._h = None
 
     def outputs(self):
