@@ -83,7 +83,7 @@ def cpu_baseline(T, x0):
     except Exception:
         cores = os.cpu_count() or 1
     xs = oracle.normalize_blocks(x0, T.shape)
-    iters = 2
+    iters = 8  # about 10 s of host work
     t0 = time.perf_counter()
     for _ in range(iters):
         sw = oracle.sweep(T, xs)

@@ -183,7 +183,9 @@ def test_singleton_modes_closed_forms(lib):
     (sigma = ||T||, u_3 = T / ||T||)."""
     rng = np.random.default_rng(71)
     A = rng.standard_normal((1, 40, 30))
-    sig, x, info = gpu_solve(lib, A, synth.init_factors(A.shape, 71), "hoscf", 1e-12, 200)
+    # top two singular values 10.74 and 10.17: HOSCF's linear rate is slow
+    # here and the oracle itself needs 229 iterations to reach 1e-12
+    sig, x, info = gpu_solve(lib, A, synth.init_factors(A.shape, 71), "hoscf", 1e-12, 1000)
     assert info.status == 0
     assert sig == pytest.approx(np.linalg.svd(A[0], compute_uv=False)[0], rel=1e-12)
     v = rng.standard_normal((1, 1, 50))
