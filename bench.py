@@ -173,7 +173,10 @@ def leg_batched(hoscf, synth, reps=1):
     terms = len(tensors) * plan.R
     out = {"workload": "4096 x order-3 FP32, dims U{8..96}, N(0,1) + U[1,20] planted, rank 8, tol 1e-6",
            "bytes": int(host.nbytes)}
-    plans = {"plain": plan, "inexact_inner": hoscf.BatchPlan(views, R=8, tol=1e-6, max_iter=500, inner_rel=1e-3)}
+    plans = {"plain": plan,
+             "inexact_inner": hoscf.BatchPlan(views, R=8, tol=1e-6, max_iter=500, inner_rel=1e-3),
+             "ihoscf": hoscf.BatchPlan(views, R=8, tol=1e-6, max_iter=500, algo="ihoscf"),
+             "ihoscf_inexact": hoscf.BatchPlan(views, R=8, tol=1e-6, max_iter=500, algo="ihoscf", inner_rel=1e-3)}
     for name, p in plans.items():
         outs = p.outputs()
         if name == "plain":

@@ -250,9 +250,12 @@ typedef struct hoscf_plan hoscf_plan;
 /*
  * hoscf_batch_plan_create -- plan for B tensors (host descriptors; each
  * order 3, FP32, every dim in [1, 96]) solved with greedy rank-one
- * deflation (Section 1; Example 3): for r = 1..R, HOSCF on
- * T_b - sum_{s<r} sigma_s u_s1 o u_s2 o u_s3.  Uploads descriptors, orders
- * work largest first and reads the tile table.  The ONLY allocating call.
+ * deflation (Section 1; Example 3): for r = 1..R, HOSCF or iHOSCF
+ * (opts->algo; Alg. 1, Section 4.4) on T_b - sum_{s<r} sigma_s u_s1 o u_s2
+ * o u_s3.  R in [1, 8]; opts->tol, max_iter, canonical_sign and inner_rel
+ * apply per term, the precision form does not (storage is FP32).  Uploads
+ * descriptors, orders work largest first and reads the tile table.  The ONLY
+ * allocating call.  HOSCF_INVALID_ARG on a bad descriptor, R or option.
  */
 int hoscf_batch_plan_create(int B, const hoscf_tensor* host_descs, int R,
                             const hoscf_options* opts, hoscf_plan** out);

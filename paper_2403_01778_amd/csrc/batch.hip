@@ -40,7 +40,8 @@ struct BatchItem {
 struct BatchArgs {
     const BatchItem* items;
     int B, R;
-    double tol, eig_tol, inner_rel;
+    double tol, eig_tol, solve_tol, inner_rel;
+    int algo;  // 0 HOSCF, 1 iHOSCF
     int max_iter, canonical;
     const double* x0;
     double* x_out;
@@ -50,8 +51,9 @@ struct BatchArgs {
     double* scratch;     // [grid][(kBatchKmax + 1) * kBatchMaxD]
     unsigned* counter;   // work queue head
     // workgroup 0's time per phase (100 MHz clock), summed over its terms:
-    // [0] deflation set-up, [1] sweep, [2] epilogue, [3] J products,
-    // [4] reorthogonalisation, [5] checks, [6] new vector, [7] normalisation
+    // [0] deflation set-up, [1] sweep, [2] epilogue, [3] eigen-step Lanczos,
+    // [4] Rayleigh-step Lanczos, [5] Rayleigh acceptance and new iterate,
+    // [7] eigen-step new iterate
     unsigned long long* prof;
 };
 
@@ -75,7 +77,8 @@ struct BatchLds {
     double defl[16 * 3];   // per previous term: sigma_s * (x_{s,k}' u_k) for the three blocks
     double xi[16];         // mode-1 entries x_{s,1}[i] of the previous terms at the current slab
     double sc[8];
-    int item, stop;
+    double theta;
+    int item, stop, ok;
 };
 
 template <int BT>
@@ -267,11 +270,214 @@ __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& 
     return fro;
 }
 
+// Lanczos on J = M / 2 from x~ = u / sqrt(3), full reorthogonalisation
+// (a second Gram-Schmidt pass only when the first removed most of the
+// vector).  mode 0: largest-magnitude Ritz pair, stopped at Ritz residual
+// <= tol * max(||J||_F, |theta|); L.s = unit Ritz vector.  mode 1: the
+// Galerkin solution t of (T_m - rho I) t = e_1 with rho = x~'J x~ (the
+// Rayleigh step), stopped at beta_m |t_m| <= tol; L.s = t, L.ok = solvable,
+// L.theta = t'T_m t / t't.  Returns m; the basis is in V.
+template <int BT>
+__device__ int batch_lanczos(BatchLds& L, const int* I, int D, double* V, int mode, double tol, double normJ) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* w = L.a.vec;                // [D]
+    double* vj = L.a.vec + kBatchMaxD;  // staged V_j
+    const double is3 = 1.0 / sqrt(3.0);
+    for (int q = tid; q < D; q += BT) {
+        V[q] = L.u[q] * is3;
+        vj[q] = L.u[q] * is3;
+    }
+    __syncthreads();
+    int m = 0;
+    bool stop = false;
+    for (int j = 0; j < kBatchKmax && !stop; ++j) {
+        bmatvec(L, I, vj, w, BT);
+        __syncthreads();
+        double nn0 = 0.0;
+        for (int q = tid; q < D; q += BT) {
+            w[q] *= 0.5;
+            nn0 = fma(w[q], w[q], nn0);
+        }
+        const double before2 = block_sum<BT>(nn0, L.red);
+        double beta = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i0 = wave; i0 <= j; i0 += BT / 64) {
+                double d = 0.0;
+                const double* Vi = V + (size_t)i0 * kBatchMaxD;
+                for (int q = lane; q < D; q += 64) d = fma(Vi[q], w[q], d);
+                for (int k = 32; k >= 1; k >>= 1) d += __shfl_xor(d, k);
+                if (lane == 0) L.h[i0] = d;
+            }
+            __syncthreads();
+            for (int q = tid; q < D; q += BT) {
+                double t = 0.0;
+                for (int i = 0; i <= j; ++i) t = fma(L.h[i], V[(size_t)i * kBatchMaxD + q], t);
+                w[q] -= t;
+            }
+            double c = 0.0;
+            for (int i = 0; i <= j; ++i) c = fma(L.h[i], L.h[i], c);
+            if (tid == 0) L.al[j] = (pass == 0 ? 0.0 : L.al[j]) + L.h[j];
+            __syncthreads();
+            if (pass == 0 && before2 - c >= 0.5 * before2) {
+                beta = sqrt(fmax(before2 - c, 0.0));  // one pass was enough (Pythagoras)
+                break;
+            }
+            if (pass == 1) {
+                double nn = 0.0;
+                for (int q = tid; q < D; q += BT) nn = fma(w[q], w[q], nn);
+                beta = sqrt(block_sum<BT>(nn, L.red));
+            }
+        }
+        if (tid == 0) {
+            L.be[j] = beta;
+            L.b2[j] = beta * beta;
+        }
+        __syncthreads();
+        m = j + 1;
+        const bool invariant = beta <= 1e-14 * normJ;
+        if (invariant || m == kBatchKmax || (m >= 3 && (m <= 8 || (m % 4) == 0))) {
+            if (mode == 0) {
+                if (tid < 64) {
+                    double lmin = L.al[0], lmax = L.al[0];
+                    if (m > 1) extreme_eigs(L.al, L.b2, L.be, m, &lmin, &lmax);
+                    if (tid == 0) {
+                        const double th = (fabs(lmin) > fabs(lmax) * (1.0 + 1e-12)) ? lmin : lmax;
+                        for (int i = 0; i < m; ++i) L.s[i] = 1.0;
+                        const double zrep = 2.220446049250313e-16 * fmax(fabs(lmin), fabs(lmax)) + 1e-300;
+                        for (int rep = 0; rep < 2; ++rep) {
+                            tri_solve(L.al, L.be, m, th, L.s, zrep, L.tri, L.tri + kBatchKmax,
+                                      L.tri + 2 * kBatchKmax, L.tri + 3 * kBatchKmax);
+                            double nrm = 0.0;
+                            for (int i = 0; i < m; ++i) nrm = fma(L.s[i], L.s[i], nrm);
+                            nrm = sqrt(nrm);
+                            for (int i = 0; i < m; ++i) L.s[i] /= nrm;
+                        }
+                        L.theta = th;
+                        const double ritz = beta * fabs(L.s[m - 1]);
+                        L.stop = (ritz <= tol * fmax(normJ, fabs(th))) || invariant || m == kBatchKmax;
+                    }
+                }
+            } else if (tid == 0) {
+                const double rho = L.al[0];
+                for (int i = 0; i < m; ++i) L.s[i] = 0.0;
+                L.s[0] = 1.0;
+                bool ok = m >= 2 && tri_solve(L.al, L.be, m, rho, L.s, 0.0, L.tri, L.tri + kBatchKmax,
+                                              L.tri + 2 * kBatchKmax, L.tri + 3 * kBatchKmax);
+                double tn = 0.0;
+                if (ok)
+                    for (int i = 0; i < m; ++i) tn = fma(L.s[i], L.s[i], tn);
+                ok = ok && isfinite(tn) && tn > 0.0;
+                L.ok = ok ? 1 : 0;
+                const double res = ok ? beta * fabs(L.s[m - 1]) : INFINITY;
+                L.stop = (m >= 2 && ok && res <= tol) || invariant || m == kBatchKmax;
+                if (L.stop && ok) {
+                    double num = 0.0;
+                    for (int i = 0; i < m; ++i) {
+                        double Tt = L.al[i] * L.s[i];
+                        if (i > 0) Tt = fma(L.be[i - 1], L.s[i - 1], Tt);
+                        if (i < m - 1) Tt = fma(L.be[i], L.s[i + 1], Tt);
+                        num = fma(L.s[i], Tt, num);
+                    }
+                    L.theta = num / tn;
+                }
+            }
+            __syncthreads();
+            stop = L.stop != 0;
+            __syncthreads();
+        }
+        if (!stop) {
+            const double ib = 1.0 / beta;
+            double* Vn = V + (size_t)(j + 1) * kBatchMaxD;
+            for (int q = tid; q < D; q += BT) {
+                const double v = w[q] * ib;
+                Vn[q] = v;
+                vj[q] = v;
+            }
+            __syncthreads();
+        }
+    }
+    return m;
+}
+
+// u = the block-normalised, sign-fixed y = V_m L.s (eq. factor); returns
+// false on a zero block.
+template <int BT>
+__device__ bool batch_new_iterate(const BatchArgs& a, BatchLds& L, int I1, int I2, int D, const double* V, int m) {
+    const int tid = threadIdx.x;
+    const int off[4] = {0, I1, I1 + I2, D};
+    double* y = L.a.vec;
+    for (int q = tid; q < D; q += BT) {
+        double t = 0.0;
+        for (int i = 0; i < m; ++i) t = fma(L.s[i], V[(size_t)i * kBatchMaxD + q], t);
+        y[q] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        bool degenerate = false;
+        double f0 = 1.0;
+        for (int n = 0; n < 3; ++n) {
+            double s2 = 0.0, bv = -1.0, bs = 0.0;
+            for (int q = off[n]; q < off[n + 1]; ++q) {
+                s2 = fma(y[q], y[q], s2);
+                if (fabs(y[q]) > bv) {
+                    bv = fabs(y[q]);
+                    bs = y[q];
+                }
+            }
+            if (!(s2 > 0.0)) degenerate = true;
+            double f = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+            if (a.canonical && n >= 1 && bs < 0.0) {
+                f = -f;
+                f0 = -f0;
+            }
+            L.sc[n] = f;
+        }
+        L.sc[0] *= f0;
+        L.stop = degenerate ? 1 : 0;
+    }
+    __syncthreads();
+    const bool degenerate = L.stop != 0;
+    if (!degenerate)
+        for (int q = tid; q < D; q += BT) {
+            const int n = q < I1 ? 0 : (q < I1 + I2 ? 1 : 2);
+            L.u[q] = y[q] * L.sc[n];
+        }
+    __syncthreads();
+    return !degenerate;
+}
+
+// Blocks of the current iterate L.u: deflation coefficients of the earlier
+// terms, then the sweep.  Returns the FP64 sum of squares of the blocks.
+template <int BT>
+__device__ double batch_sweep_at_u(const BatchArgs& a, BatchLds& L, const BatchItem& item, int r, int I1, int I2,
+                                   int D) {
+    const int tid = threadIdx.x;
+    // defl[3s + c]: c = 0 for block (1,2) (third mode 3), 1 for (1,3)
+    // (mode 2), 2 for (2,3) (mode 1): sigma_s * x_{s,k}' u_k
+    for (int s = 0; s < r; ++s) {
+        const double* xs = a.x_out + item.xoff + (int64_t)s * D;
+        const double sg = a.sigma_out[item.b * a.R + s];
+        for (int c = 0; c < 3; ++c) {
+            const int lo = c == 0 ? I1 + I2 : (c == 1 ? I1 : 0);
+            const int hi = c == 0 ? D : (c == 1 ? I1 + I2 : I1);
+            double d = 0.0;
+            for (int q = lo + tid; q < hi; q += BT) d = fma(xs[q], L.u[q], d);
+            d = block_sum<BT>(d, L.red);
+            if (tid == 0) L.defl[3 * s + c] = sg * d;
+        }
+    }
+    for (int q = tid; q < D; q += BT) L.uf[q] = (float)L.u[q];
+    __syncthreads();
+    const bool vec_ok = ((item.I[1] * item.I[2]) % 4) == 0 && (reinterpret_cast<uintptr_t>(item.T) & 15) == 0;
+    const double f = vec_ok ? batch_sweep<BT, 4>(a, L, item, r, D) : batch_sweep<BT, 1>(a, L, item, r, D);
+    return block_sum<BT>(f, L.red);  // includes the barrier after the block writes
+}
+
 template <int BT>
 __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BatchLds& L = *reinterpret_cast<BatchLds*>(lds_raw);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     double* V = a.scratch + (size_t)blockIdx.x * (kBatchKmax + 1) * kBatchMaxD;
     const bool tr = blockIdx.x == 0 && tid == 0;
     unsigned long long tprev = tr ? __builtin_amdgcn_s_memrealtime() : 0ull;
@@ -290,13 +496,9 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
         if (it >= a.B) break;
         const BatchItem item = a.items[it];
         const int I[3] = {item.I[0], item.I[1], item.I[2]};
-        const int I1 = I[0], I2 = I[1], I3 = I[2];
+        const int I1 = I[0], I2 = I[1];
         const int D = item.D;
         const int off[4] = {0, I1, I1 + I2, D};
-        const int n23 = I2 * I3;
-        float* A12 = L.blk;
-        float* A13 = A12 + I1 * I2;
-        float* A23 = A13 + I1 * I3;
 
         for (int r = 0; r < a.R; ++r) {
             const double* x0 = a.x0 + item.xoff + (int64_t)r * D;
@@ -321,30 +523,15 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
             }
             __syncthreads();
 
+            bool have_blocks = false;  // a rejected Rayleigh step left the blocks of u in LDS
+            double fro = 0.0;
             while (status == HOSCF_NOT_CONVERGED) {
-                // ---- deflation coefficients of the previous terms at u ----
-                // defl[3s + c]: c = 0 for block (1,2) (third mode 3), 1 for (1,3)
-                // (mode 2), 2 for (2,3) (mode 1): sigma_s * x_{s,k}' u_k
-                for (int s = 0; s < r; ++s) {
-                    const double* xs = a.x_out + item.xoff + (int64_t)s * D;
-                    const double sg = a.sigma_out[item.b * a.R + s];
-                    for (int c = 0; c < 3; ++c) {
-                        const int k = 2 - c;
-                        double d = 0.0;
-                        for (int q = off[k] + tid; q < off[k + 1]; q += BT) d = fma(xs[q], L.u[q], d);
-                        d = block_sum<BT>(d, L.red);
-                        if (tid == 0) L.defl[3 * s + c] = sg * d;
-                    }
+                if (!have_blocks) {
+                    BATCH_ACC(0);
+                    fro = batch_sweep_at_u<BT>(a, L, item, r, I1, I2, D);
+                    BATCH_ACC(1);
                 }
-                for (int q = tid; q < D; q += BT) L.uf[q] = (float)L.u[q];
-                __syncthreads();
-                BATCH_ACC(0);
-
-                // ---- sweep: blocks at u, FP64 accumulation ----
-                const bool vec_ok = (n23 % 4) == 0 && (reinterpret_cast<uintptr_t>(item.T) & 15) == 0;
-                double fro = vec_ok ? batch_sweep<BT, 4>(a, L, item, r, D) : batch_sweep<BT, 1>(a, L, item, r, D);
-                fro = block_sum<BT>(fro, L.red);  // includes the barrier after the block writes
-                BATCH_ACC(1);
+                have_blocks = false;
 
                 // ---- g = M u / 2, sigma, ||J||_F, residual ----
                 bmatvec(L, I, L.u, L.g, BT);
@@ -379,133 +566,34 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs a) {
                 if (iters >= a.max_iter) break;
                 ++iters;
 
-                // ---- eigen-step: Lanczos on J = M/2 from x~ = u/sqrt(3) ----
-                // (inexact when inner_rel > 0: accurate relative to the residual)
-                const double eig_tol = fmax(a.eig_tol, a.inner_rel > 0.0 ? fmin(1e-3, a.inner_rel * res) : 0.0);
-                double* w = L.a.vec;                 // [D]
-                double* vj = L.a.vec + kBatchMaxD;   // staged V_j
-                const double is3 = 1.0 / sqrt(3.0);
-                for (int q = tid; q < D; q += BT) {
-                    V[q] = L.u[q] * is3;
-                    vj[q] = L.u[q] * is3;
-                }
-                __syncthreads();
-                int m = 0;
-                bool stop = false;
-                for (int j = 0; j < kBatchKmax && !stop; ++j) {
-                    bmatvec(L, I, vj, w, BT);
-                    __syncthreads();
-                    for (int q = tid; q < D; q += BT) w[q] *= 0.5;
-                    __syncthreads();
-                    BATCH_ACC(3);
-                    // two passes of classical Gram-Schmidt against V_0..V_j
-                    for (int pass = 0; pass < 2; ++pass) {
-                        for (int i0 = wave; i0 <= j; i0 += BT / 64) {
-                            double d = 0.0;
-                            const double* Vi = V + (size_t)i0 * kBatchMaxD;
-                            for (int q = lane; q < D; q += 64) d = fma(Vi[q], w[q], d);
-                            for (int k = 32; k >= 1; k >>= 1) d += __shfl_xor(d, k);
-                            if (lane == 0) L.h[i0] = d;
-                        }
-                        __syncthreads();
-                        for (int q = tid; q < D; q += BT) {
-                            double t = 0.0;
-                            for (int i = 0; i <= j; ++i) t = fma(L.h[i], V[(size_t)i * kBatchMaxD + q], t);
-                            w[q] -= t;
-                        }
-                        if (tid == 0) L.al[j] = (pass == 0 ? 0.0 : L.al[j]) + L.h[j];
-                        __syncthreads();
-                    }
-                    double nn = 0.0;
-                    for (int q = tid; q < D; q += BT) nn = fma(w[q], w[q], nn);
-                    const double beta = sqrt(block_sum<BT>(nn, L.red));
-                    if (tid == 0) {
-                        L.be[j] = beta;
-                        L.b2[j] = beta * beta;
-                    }
-                    __syncthreads();
-                    m = j + 1;
-                    BATCH_ACC(4);
-                    const bool invariant = beta <= 1e-14 * normJ;
-                    if (invariant || m == kBatchKmax || (m >= 3 && (m <= 8 || (m % 4) == 0))) {
-                        if (tid < 64) {
-                            double lmin = L.al[0], lmax = L.al[0];
-                            if (m > 1) extreme_eigs(L.al, L.b2, L.be, m, &lmin, &lmax);
-                            if (tid == 0) {
-                                const double th = (fabs(lmin) > fabs(lmax) * (1.0 + 1e-12)) ? lmin : lmax;
-                                for (int i = 0; i < m; ++i) L.s[i] = 1.0;
-                                const double zrep = 2.220446049250313e-16 * fmax(fabs(lmin), fabs(lmax)) + 1e-300;
-                                for (int rep = 0; rep < 3; ++rep) {
-                                    tri_solve(L.al, L.be, m, th, L.s, zrep, L.tri, L.tri + kBatchKmax,
-                                              L.tri + 2 * kBatchKmax, L.tri + 3 * kBatchKmax);
-                                    double nrm = 0.0;
-                                    for (int i = 0; i < m; ++i) nrm = fma(L.s[i], L.s[i], nrm);
-                                    nrm = sqrt(nrm);
-                                    for (int i = 0; i < m; ++i) L.s[i] /= nrm;
-                                }
-                                const double ritz = beta * fabs(L.s[m - 1]);
-                                L.stop = (ritz <= eig_tol * fmax(normJ, fabs(th))) || invariant || m == kBatchKmax;
-                            }
-                        }
-                        __syncthreads();
-                        stop = L.stop != 0;
-                        __syncthreads();
-                    }
-                    BATCH_ACC(5);
-                    if (!stop) {
-                        const double ib = 1.0 / beta;
-                        double* Vn = V + (size_t)(j + 1) * kBatchMaxD;
-                        for (int q = tid; q < D; q += BT) {
-                            const double v = w[q] * ib;
-                            Vn[q] = v;
-                            vj[q] = v;
-                        }
-                        __syncthreads();
-                    }
-                }
-                BATCH_ACC(6);
-                // y = V_m s, block norms and largest-|entry| signs
-                double* y = w;
-                for (int q = tid; q < D; q += BT) {
-                    double t = 0.0;
-                    for (int i = 0; i < m; ++i) t = fma(L.s[i], V[(size_t)i * kBatchMaxD + q], t);
-                    y[q] = t;
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    bool degenerate = false;
-                    double f0 = 1.0;
-                    for (int n = 0; n < 3; ++n) {
-                        double s2 = 0.0, bv = -1.0, bs = 0.0;
-                        for (int q = off[n]; q < off[n + 1]; ++q) {
-                            s2 = fma(y[q], y[q], s2);
-                            if (fabs(y[q]) > bv) {
-                                bv = fabs(y[q]);
-                                bs = y[q];
-                            }
-                        }
-                        if (!(s2 > 0.0)) degenerate = true;
-                        double f = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-                        if (a.canonical && n >= 1 && bs < 0.0) {
-                            f = -f;
-                            f0 = -f0;
-                        }
-                        L.sc[n] = f;
-                    }
-                    L.sc[0] *= f0;
-                    L.stop = degenerate ? 1 : 0;
-                }
-                __syncthreads();
-                if (L.stop) {
+                // ---- eigen-step (inexact when inner_rel > 0) ----
+                const double loose = a.inner_rel > 0.0 ? fmin(1e-3, a.inner_rel * res) : 0.0;
+                int m = batch_lanczos<BT>(L, I, D, V, 0, fmax(a.eig_tol, loose), normJ);
+                BATCH_ACC(3);
+                if (!batch_new_iterate<BT>(a, L, I1, I2, D, V, m)) {
                     status = HOSCF_DEGENERATE;
                     break;
                 }
-                for (int q = tid; q < D; q += BT) {
-                    const int n = q < I1 ? 0 : (q < I1 + I2 ? 1 : 2);
-                    L.u[q] = y[q] * L.sc[n];
-                }
-                __syncthreads();
                 BATCH_ACC(7);
+
+                // ---- iHOSCF Rayleigh step at the new iterate ----
+                if (a.algo == 1) {
+                    fro = batch_sweep_at_u<BT>(a, L, item, r, I1, I2, D);
+                    const double normJ2 = sqrt(2.0 * fro) * 0.5;
+                    m = batch_lanczos<BT>(L, I, D, V, 1, fmax(a.solve_tol, loose), normJ2);
+                    BATCH_ACC(4);
+                    const bool accept = L.ok != 0 && fabs(L.theta) > fabs(L.al[0]);
+                    __syncthreads();
+                    if (accept) {
+                        if (!batch_new_iterate<BT>(a, L, I1, I2, D, V, m)) {
+                            status = HOSCF_DEGENERATE;
+                            break;
+                        }
+                    } else {
+                        have_blocks = true;
+                    }
+                    BATCH_ACC(5);
+                }
             }
             // final sign fix: sigma >= 0 via u_1
             const bool flip = sigma < 0.0;
@@ -575,7 +663,8 @@ int hoscf_batch_plan_create(int B, const hoscf_tensor* descs, int R, const hoscf
     o.max_iter = 500;
     o.canonical_sign = 1;
     if (opts) o = *opts;
-    if (o.algo != 0 || !(o.tol >= 0.0) || o.max_iter < 0 || !(o.inner_rel >= 0.0)) return HOSCF_INVALID_ARG;
+    if ((o.algo != 0 && o.algo != 1) || !(o.tol >= 0.0) || o.max_iter < 0 || !(o.inner_rel >= 0.0))
+        return HOSCF_INVALID_ARG;
     std::vector<BatchItem> items((size_t)B);
     int64_t xoff = 0;
     for (int b = 0; b < B; ++b) {
@@ -640,7 +729,9 @@ int hoscf_solve_batched(const hoscf_plan* plan, const double* x0, double* x_out,
     a.R = plan->R;
     a.tol = plan->opts.tol;
     a.eig_tol = std::min(1e-8, std::max(1e-13, 1e-3 * plan->opts.tol));
+    a.solve_tol = std::min(1e-8, std::max(1e-13, 1e-2 * plan->opts.tol));
     a.inner_rel = plan->opts.inner_rel;
+    a.algo = plan->opts.algo;
     a.max_iter = plan->opts.max_iter;
     a.canonical = plan->opts.canonical_sign;
     a.x0 = x0;

@@ -368,11 +368,12 @@ def solve(T: torch.Tensor, x0: torch.Tensor, **opts) -> Tuple[torch.Tensor, torc
 
 class BatchPlan:
     """Plan for the batched form (hoscf_batch_plan_create): B order-3 FP32
-    device tensors (dims <= 96), R rank-one terms each by greedy deflation.
+    device tensors (dims <= 96), R <= 8 rank-one terms each by greedy
+    deflation, each term by HOSCF or iHOSCF (`algo`).
     Keeps the tensors alive; frees the plan on deletion."""
 
     def __init__(self, tensors: Sequence[torch.Tensor], R: int, tol: float = 1e-6, max_iter: int = 500,
-                 canonical_sign: bool = True, inner_rel: float = 0.0):
+                 canonical_sign: bool = True, inner_rel: float = 0.0, algo: str = "hoscf"):
         self.tensors = [t.contiguous() for t in tensors]
         self.R = int(R)
         self.dims = [tuple(int(d) for d in t.shape) for t in self.tensors]
@@ -386,7 +387,7 @@ class BatchPlan:
         descs = (HoscfTensor * max(1, len(self.tensors)))()
         for i, t in enumerate(self.tensors):
             descs[i] = describe(t)
-        opts = options(algo="hoscf", tol=tol, max_iter=max_iter, canonical_sign=canonical_sign, inner_rel=inner_rel)
+        opts = options(algo=algo, tol=tol, max_iter=max_iter, canonical_sign=canonical_sign, inner_rel=inner_rel)
         h = ctypes.c_void_p()
         _check(_lib.hoscf_batch_plan_create(len(self.tensors), descs, self.R, ctypes.byref(opts), ctypes.byref(h)),
                "hoscf_batch_plan_create")

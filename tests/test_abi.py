@@ -118,7 +118,13 @@ def test_batch_plan_rejects_bad_descriptors(lib):
     assert create([ok, _desc(lib, [8, 9, 10], data=0)], 2)[0] == lib.INVALID_ARG   # null data
     assert create([ok], 0)[0] == lib.INVALID_ARG                                # R < 1
     assert create([ok], 9)[0] == lib.INVALID_ARG                                # R > 8
-    assert create([ok], 2, lib.options(algo="ihoscf"))[0] == lib.INVALID_ARG   # HOSCF only
+    bad_algo = lib.options(algo="hoscf")
+    bad_algo.algo = 2
+    assert create([ok], 2, bad_algo)[0] == lib.INVALID_ARG
+    rc, h = create([ok], 2, lib.options(algo="ihoscf"))  # iHOSCF is accepted
+    assert rc != lib.INVALID_ARG  # (without a GPU the device upload itself fails)
+    if rc == lib.OK:
+        so.hoscf_plan_destroy(h)
     assert create([ok], 2, lib.options(algo="hoscf", inner_rel=-1.0))[0] == lib.INVALID_ARG
     # an empty batch is a valid no-op plan
     rc, h = create([], 2)
