@@ -14,7 +14,9 @@
 // Layout of the work: lanes own 16-byte vectors of consecutive q (VEC
 // elements), LR lanes per row, G = 64/LR rows per wave instruction.  A wave
 // holds R for its MB rows per group in registers while it streams over a
-// p-range, flushes C once per p (the four waves of a workgroup share the
+// p-range, refilling each row's load registers with the next slab's row as
+// soon as the row is consumed (MB - 1 to MB rows stay in flight with one
+// buffer, which leaves room for twice the rows per workgroup), flushes C once per p (the four waves of a workgroup share the
 // q-chunk and p-range and combine their C contributions in LDS, in a fixed
 // order), and reduces L per row with a transposed butterfly over its lanes.
 // Every reduction has a fixed order, so a sweep is bitwise reproducible.
@@ -22,6 +24,9 @@
 #include "ttvc.h"
 
 #include <algorithm>
+#include <mutex>
+#include <type_traits>
+#include <unordered_map>
 
 namespace hoscf {
 
@@ -156,7 +161,8 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     __shared__ A lbuf[LBUF ? 2 * KS * NW * WM : 1];
     __shared__ A cres[2 * KS * QW];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: row indices live in SGPRs
     const int g = lane / LR, c = lane % LR;
     const int64_t P = args.P, M = args.M, Q = args.Q;
     // Workgroups are dealt round-robin to the 8 XCDs.  Renumber them so that
@@ -174,6 +180,9 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
 
     const int64_t q0 = (int64_t)qc * args.QWe + (int64_t)c * VEC;
     const bool qok = (c * VEC < args.QWe) && (q0 < Q);
+    // lane offset within the chunk; lanes past the chunk read its first
+    // vector (in bounds) and then select zero
+    const int64_t qoff = qok ? (int64_t)c * VEC : 0;
     const int64_t mrow0 = (mtw * NW + wave) * WM + g;
     const int64_t p0 = pt * args.BP;
     const int64_t p1 = p0 + args.BP < P ? p0 + args.BP : P;
@@ -205,7 +214,16 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     A* Cout = static_cast<A*>(args.C);
     int slot = 0, par = 0, nflush = 0;
     // Body of one p-slab: R, C and the row dots for L from MB rows in `raw`.
-    auto body = [&](const typename L::Raw* raw, int64_t p) {
+    // Unconditional load of row i of slab p (the row index clamped into the
+    // tensor) followed by a select: no branch around the load, so the row's
+    // arithmetic stays ahead of its refill.
+    auto ld = [&](int64_t p, int i, int qo) -> typename L::Raw {
+        const int64_t m = mrow0 + (int64_t)G * i;
+        const int64_t mc = m < M ? m : M - 1;
+        const typename L::Raw r = L::load(Tb + (p * M + mc) * Q + (int64_t)qc * args.QWe + qo);
+        return rok[i] ? r : L::zero();
+    };
+    auto body = [&](auto refill, typename L::Raw* raw, int64_t p) {
         const A xpp = xp[p];
         A accC[VEC];
 #pragma unroll
@@ -223,6 +241,17 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
                 d = fma(e[v], xqv[v], d);
             }
             dl[i] = d;
+            // rolling prefetch: row i of the next slab goes into the
+            // registers just consumed
+            if constexpr (decltype(refill)::value) {
+                // the refill's address depends on this row's results, so it
+                // cannot be issued before the row is consumed
+                int qo = (int)qoff;
+                asm volatile("" : "+v"(qo) : "v"(d));
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) asm volatile("" : "+v"(qo) : "v"(accR[i][v]), "v"(accC[v]));
+                raw[i] = ld(p + 1, i, qo);
+            }
         }
         if (args.doL) {
             int base = 0;
@@ -292,21 +321,14 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
             }
         }
     };
-    auto fetch = [&](typename L::Raw* raw, int64_t p) {
-        const S* rowp = Tb + (p * M + mrow0) * Q + q0;
+    // One register buffer refilled row by row: MB - 1 to MB rows of loads
+    // stay in flight per wave.
+    typename L::Raw buf[MB];
+    if (p0 < p1) {
 #pragma unroll
-        for (int i = 0; i < MB; ++i) raw[i] = rok[i] ? L::load(rowp + (int64_t)i * G * Q) : L::zero();
-    };
-    // Two register buffers: the rows of slab p + 1 are requested before slab p
-    // is consumed, so each wave keeps a full slab of loads in flight.
-    typename L::Raw buf0[MB], buf1[MB];
-    if (p0 < p1) fetch(buf0, p0);
-    for (int64_t p = p0; p < p1; p += 2) {
-        if (p + 1 < p1) fetch(buf1, p + 1);
-        body(buf0, p);
-        if (p + 1 >= p1) break;
-        if (p + 2 < p1) fetch(buf0, p + 2);
-        body(buf1, p + 1);
+        for (int i = 0; i < MB; ++i) buf[i] = ld(p0, i, (int)qoff);
+        for (int64_t p = p0; p < p1 - 1; ++p) body(std::true_type{}, buf, p);
+        body(std::false_type{}, buf, p1 - 1);
     }
     if (args.doR) {
 #pragma unroll
@@ -440,60 +462,62 @@ static int pow2_at_least(int64_t v) {
 // Rows per lane-group for each storage format (register budget of R).
 template <int FMT> constexpr int mb_vec() { return FMT == HOSCF_F64 ? 16 : FMT == HOSCF_F32 ? 16 : FMT == HOSCF_BF16 ? 8 : 4; }
 
+// The level-1 instance for a lane count (instantiated: every LR with full
+// rows and 4 waves; LR >= 8 with half rows; LR >= 16 with 8 waves).
 template <int FMT, int VEC, int MB, int NW>
-static hipError_t launch_lr(int LR, dim3 grid, const Ttvc3Args& a, hipStream_t s) {
-    const dim3 blk(NW * 64);
+static const void* k1_ptr(int LR) {
     constexpr bool base = (MB == mb_vec<FMT>() && NW == 4);
     switch (LR) {
-        case 1: if constexpr (base) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 1, MB, NW>), grid, blk, 0, s, a); break;
-        case 2: if constexpr (base) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 2, MB, NW>), grid, blk, 0, s, a); break;
-        case 4: if constexpr (base) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 4, MB, NW>), grid, blk, 0, s, a); break;
-        case 8: if constexpr (NW == 4) hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 8, MB, NW>), grid, blk, 0, s, a); break;
-        case 16: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 16, MB, NW>), grid, blk, 0, s, a); break;
-        case 32: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 32, MB, NW>), grid, blk, 0, s, a); break;
-        default: hipLaunchKernelGGL((ttvc3_kernel<FMT, VEC, 64, MB, NW>), grid, blk, 0, s, a); break;
+        case 1: if constexpr (base) return (const void*)&ttvc3_kernel<FMT, VEC, 1, MB, NW>; break;
+        case 2: if constexpr (base) return (const void*)&ttvc3_kernel<FMT, VEC, 2, MB, NW>; break;
+        case 4: if constexpr (base) return (const void*)&ttvc3_kernel<FMT, VEC, 4, MB, NW>; break;
+        case 8: if constexpr (NW == 4) return (const void*)&ttvc3_kernel<FMT, VEC, 8, MB, NW>; break;
+        case 16: return (const void*)&ttvc3_kernel<FMT, VEC, 16, MB, NW>;
+        case 32: return (const void*)&ttvc3_kernel<FMT, VEC, 32, MB, NW>;
+        default: return (const void*)&ttvc3_kernel<FMT, VEC, 64, MB, NW>;
     }
-    return hipGetLastError();
+    return nullptr;
 }
 
-// Resident workgroups of the three-output kernel per CU (register-limited),
-// and the CU count, for grid sizing.
-static int resident_slots(int fmt, int VEC, int LR) {
-    static int cached[4][2][8] = {};
-    const int li = LR == 1 ? 0 : LR == 2 ? 1 : LR == 4 ? 2 : LR == 8 ? 3 : LR == 16 ? 4 : LR == 32 ? 5 : 6;
-    int& c = cached[fmt][VEC > 1][li];
-    if (c) return c;
-    int dev = 0, cus = 256, per = 2;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void* fn = nullptr;
-#define HOSCF_FN(F, V, MB)                                                                               \
-    switch (LR) {                                                                                        \
-        case 1: fn = (const void*)&ttvc3_kernel<F, V, 1, MB>; break;                                     \
-        case 2: fn = (const void*)&ttvc3_kernel<F, V, 2, MB>; break;                                     \
-        case 4: fn = (const void*)&ttvc3_kernel<F, V, 4, MB>; break;                                     \
-        case 8: fn = (const void*)&ttvc3_kernel<F, V, 8, MB>; break;                                     \
-        case 16: fn = (const void*)&ttvc3_kernel<F, V, 16, MB>; break;                                   \
-        case 32: fn = (const void*)&ttvc3_kernel<F, V, 32, MB>; break;                                   \
-        default: fn = (const void*)&ttvc3_kernel<F, V, 64, MB>; break;                                   \
+template <int FMT>
+static const void* k1_instance(const Ttvc3Shape& sh) {
+    constexpr int V = Fmt<FMT>::VEC;
+    constexpr int MBV = mb_vec<FMT>();
+    if (sh.VEC == V) {
+        const bool half = sh.MB == MBV / 2 && sh.LR >= 8;
+        if (sh.NW == 8 && sh.LR >= 16) return half ? k1_ptr<FMT, V, MBV / 2, 8>(sh.LR) : k1_ptr<FMT, V, MBV, 8>(sh.LR);
+        return half ? k1_ptr<FMT, V, MBV / 2, 4>(sh.LR) : k1_ptr<FMT, V, MBV, 4>(sh.LR);
     }
-    if (VEC == 1) {
-        switch (fmt) {
-            case HOSCF_F64: fn = (const void*)&ttvc3_kernel<HOSCF_F64, 1, 64, 16>; break;
-            case HOSCF_F32: fn = (const void*)&ttvc3_kernel<HOSCF_F32, 1, 64, 16>; break;
-            case HOSCF_BF16: fn = (const void*)&ttvc3_kernel<HOSCF_BF16, 1, 64, 16>; break;
-            default: fn = (const void*)&ttvc3_kernel<HOSCF_FP8E4M3, 1, 64, 16>; break;
-        }
-    } else {
-        switch (fmt) {
-            case HOSCF_F64: HOSCF_FN(HOSCF_F64, 2, 16); break;
-            case HOSCF_F32: HOSCF_FN(HOSCF_F32, 4, 16); break;
-            case HOSCF_BF16: HOSCF_FN(HOSCF_BF16, 8, 8); break;
-            default: HOSCF_FN(HOSCF_FP8E4M3, 16, 4); break;
-        }
+    return (const void*)&ttvc3_kernel<FMT, 1, 64, 16>;
+}
+
+// The kernel a shape launches (block: NW waves); nullptr if not instantiated.
+static const void* k1_fn(int fmt, const Ttvc3Shape& sh) {
+    switch (fmt) {
+        case HOSCF_F64: return k1_instance<HOSCF_F64>(sh);
+        case HOSCF_F32: return k1_instance<HOSCF_F32>(sh);
+        case HOSCF_BF16: return k1_instance<HOSCF_BF16>(sh);
+        case HOSCF_FP8E4M3: return k1_instance<HOSCF_FP8E4M3>(sh);
     }
-#undef HOSCF_FN
-    if (fn) hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0);
-    c = std::max(1, cus * std::max(1, per));
+    return nullptr;
+}
+
+// Workgroups of that kernel resident on the whole GPU at once (registers and
+// LDS decide), for grid sizing.  Cached per instance.
+static int resident_slots(int fmt, const Ttvc3Shape& sh) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    const void* fn = k1_fn(fmt, sh);
+    if (!fn) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(fn);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, sh.NW * 64, 0) != hipSuccess) per = 1;
+    const int c = std::max(1, cus * std::max(1, per));
+    cache[fn] = c;
     return c;
 }
 
@@ -528,8 +552,7 @@ Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, const SweepTuni
     const int64_t cols = (int64_t)s.nq * s.nmt;
     // p-split: balance rounds of resident workgroups against the R partials it
     // creates (npt copies of M x Q accumulators, written and read back).
-    const int64_t slots = target_wg > 0 ? target_wg
-                                        : std::max<int64_t>(1, resident_slots(fmt, s.VEC, s.LR) * 4 / s.NW);
+    const int64_t slots = target_wg > 0 ? target_wg : std::max<int64_t>(1, resident_slots(fmt, s));
     const double tbytes = (double)P * (double)M * (double)Q * esz[fmt];
     const double accb = fmt == HOSCF_F64 ? 8.0 : 4.0;
     double best = 1e300;
@@ -554,29 +577,12 @@ Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, const SweepTuni
     return s;
 }
 
-template <int FMT>
-static hipError_t launch_ttvc3_fmt(const Ttvc3Shape& sh, const Ttvc3Args& a, hipStream_t s) {
-    const dim3 grid((unsigned)((int64_t)sh.nq * sh.nmt * sh.npt));
-    constexpr int V = Fmt<FMT>::VEC;
-    constexpr int MBV = mb_vec<FMT>();
-    if (sh.VEC == V) {
-        const bool half = sh.MB == MBV / 2 && sh.LR >= 8;
-        if (sh.NW == 8 && sh.LR >= 16)
-            return half ? launch_lr<FMT, V, MBV / 2, 8>(sh.LR, grid, a, s) : launch_lr<FMT, V, MBV, 8>(sh.LR, grid, a, s);
-        return half ? launch_lr<FMT, V, MBV / 2, 4>(sh.LR, grid, a, s) : launch_lr<FMT, V, MBV, 4>(sh.LR, grid, a, s);
-    }
-    hipLaunchKernelGGL((ttvc3_kernel<FMT, 1, 64, 16>), grid, dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_ttvc3(int fmt, const Ttvc3Shape& sh, const Ttvc3Args& a, hipStream_t s) {
-    switch (fmt) {
-        case HOSCF_F64: return launch_ttvc3_fmt<HOSCF_F64>(sh, a, s);
-        case HOSCF_F32: return launch_ttvc3_fmt<HOSCF_F32>(sh, a, s);
-        case HOSCF_BF16: return launch_ttvc3_fmt<HOSCF_BF16>(sh, a, s);
-        case HOSCF_FP8E4M3: return launch_ttvc3_fmt<HOSCF_FP8E4M3>(sh, a, s);
-    }
-    return hipErrorInvalidValue;
+    const void* fn = k1_fn(fmt, sh);
+    if (!fn) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((int64_t)sh.nq * sh.nmt * sh.npt));
+    void* kargs[] = {const_cast<Ttvc3Args*>(&a)};
+    return hipLaunchKernel(fn, grid, dim3(sh.NW * 64), kargs, 0, s);
 }
 
 hipError_t launch_reduce(bool f64, const ReduceJobs& jobs, int njobs, hipStream_t s) {

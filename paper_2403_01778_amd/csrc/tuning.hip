@@ -45,19 +45,15 @@ SweepTuning lookup_tuning(const hoscf_tensor& T) {
             if (same_shape(e, T)) return tuning_from(e.tiling);
     }
     // Built-in rule, from level-1 sweeps measured on MI355X (FP32 800^3,
-    // 200^4, 64^5): for order 3 the C partials (one P x Q copy per m-tile)
-    // dominate the output traffic, and halving the rows per lane group
-    // with 4 waves was fastest; for order >= 4 the L intermediate is the
-    // large output, and full rows per lane group with 8 waves was fastest.
-    static const int mbs[4] = {16, 16, 8, 4};
+    // 200^4, 64^5; BF16 and FP8 64^5): with the row-by-row refill, full rows
+    // per lane group and 8 waves (128 rows of a workgroup for FP32) were
+    // fastest at every order: the partial outputs per m-tile, written while
+    // T streams, cost far more per byte than the reads, and bigger tiles
+    // write fewer of them.
+    (void)T;
     SweepTuning s;
-    if (T.order == 3) {
-        s.mb = mbs[T.dtype] / 2;
-        s.nw = 4;
-    } else {
-        s.mb = 0;
-        s.nw = 8;
-    }
+    s.mb = 0;
+    s.nw = 8;
     return s;
 }
 
