@@ -183,7 +183,9 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     // lane offset within the chunk; lanes past the chunk read its first
     // vector (in bounds) and then select zero
     const int64_t qoff = qok ? (int64_t)c * VEC : 0;
-    const int64_t mrow0 = (mtw * NW + wave) * WM + g;
+    // m-tiles split M evenly: tile mtw holds rows [mlo, mhi), at most NW * WM
+    const int64_t mlo = mtw * M / args.nmt, mhi = (mtw + 1) * M / args.nmt;
+    const int64_t mrow0 = mlo + (int64_t)wave * WM + g;
     const int64_t p0 = pt * args.BP;
     const int64_t p1 = p0 + args.BP < P ? p0 + args.BP : P;
     const A* xp = static_cast<const A*>(args.xp);
@@ -199,8 +201,8 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         const int64_t m = mrow0 + (int64_t)G * i;
-        rok[i] = qok && (m < M);
-        wm[i] = (m < M) ? w[m] : A(0);
+        rok[i] = qok && (m < mhi);
+        wm[i] = (m < mhi) ? w[m] : A(0);
     }
     A accR[MB][VEC];
 #pragma unroll
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     // arithmetic stays ahead of its refill.
     auto ld = [&](int64_t p, int i, int qo) -> typename L::Raw {
         const int64_t m = mrow0 + (int64_t)G * i;
-        const int64_t mc = m < M ? m : M - 1;
+        const int64_t mc = m < mhi ? m : mhi - 1;
         const typename L::Raw r = L::load(Tb + (p * M + mc) * Q + (int64_t)qc * args.QWe + qo);
         return rok[i] ? r : L::zero();
     };
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
                         lbuf[(par * KS + slot) * NW * WM + wave * WM + rl] = dl[j];
                     } else {
                         const int64_t m = mrow0 - g + rl;
-                        if (m < M) Lout[((int64_t)qc * P + p) * M + m] = dl[j] * scale;
+                        if (m < mhi) Lout[((int64_t)qc * P + p) * M + m] = dl[j] * scale;
                     }
                 }
             }
@@ -308,9 +310,9 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
                             const int nval = slot * NW * WM;
                             for (int idx = tid; idx < nval; idx += NT) {
                                 const int s = idx / (NW * WM), k = idx - s * (NW * WM);
-                                const int64_t m = mtw * NW * WM + k;
+                                const int64_t m = mlo + k;
                                 const int64_t pp = p - slot + 1 + s;
-                                if (m < M) Lout[((int64_t)qc * P + pp) * M + m] = lbuf[par * KS * NW * WM + idx] * scale;
+                                if (m < mhi) Lout[((int64_t)qc * P + pp) * M + m] = lbuf[par * KS * NW * WM + idx] * scale;
                             }
                         }
                     }
@@ -325,10 +327,18 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     // stay in flight per wave.
     typename L::Raw buf[MB];
     if (p0 < p1) {
+        if (mrow0 - g < mhi) {
 #pragma unroll
-        for (int i = 0; i < MB; ++i) buf[i] = ld(p0, i, (int)qoff);
-        for (int64_t p = p0; p < p1 - 1; ++p) body(std::true_type{}, buf, p);
-        body(std::false_type{}, buf, p1 - 1);
+            for (int i = 0; i < MB; ++i) buf[i] = ld(p0, i, (int)qoff);
+            for (int64_t p = p0; p < p1 - 1; ++p) body(std::true_type{}, buf, p);
+            body(std::false_type{}, buf, p1 - 1);
+        } else {
+            // every row of this wave is past M (the last m-tile): no loads,
+            // zero contributions, the same flush barriers as the other waves
+#pragma unroll
+            for (int i = 0; i < MB; ++i) buf[i] = L::zero();
+            for (int64_t p = p0; p < p1; ++p) body(std::false_type{}, buf, p);
+        }
     }
     if (args.doR) {
 #pragma unroll
