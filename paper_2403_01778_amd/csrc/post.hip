@@ -215,16 +215,19 @@ struct Vec16<double> {
 
 // Raw (N-1) J v for the workgroup's own rows, written to out[r]; returns the
 // thread's share of the sum over own rows of ||row||^2 when want_fro.  v is
-// staged in LDS when it fits.  A wave takes one row at a time; each segment of
-// the row (a row of a stored block or of its transpose) is read with 16-byte
-// loads, four per lane in flight, when its length and address allow, else
-// element by element.
+// staged in LDS when it fits.  A wave takes two rows of the same mode at a
+// time (rows r and r + waves): both rows' loads of a segment (a row of a
+// stored block or of its transpose) are in flight together and share the
+// reads of v, which halves the memory round trips per row.  Segments are read
+// with 16-byte loads, four per lane and row in flight, when their length and
+// address allow, else element by element.
 template <typename B, bool COHERENT>
 __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, double scale, bool want_fro,
                               int64_t r_lo, int64_t r_hi, double* vlds) {
     using VT = typename Vec16<B>::T;
     constexpr int E = Vec16<B>::E;
     constexpr int U = 4;
+    constexpr int NWV = BS / 64;
     const B* blocks = static_cast<const B*>(a.blocks);
     const B* bt = static_cast<const B*>(a.blocksT);
     const int lane = threadIdx.x & 63;
@@ -236,65 +239,89 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
     }
     const double* vv = staged ? vlds : v;
     double fro = 0.0;
-    for (int64_t r = r_lo + wave; r < r_hi; r += BS / 64) {
+    int64_t r = r_lo + wave;
+    while (r < r_hi) {
         int n = 0;
         while (r >= a.xoff[n + 1]) ++n;
         const int64_t i = r - a.xoff[n];
-        double acc = 0.0;
+        const int64_t r2 = r + NWV;
+        const bool pair = r2 < r_hi && r2 < a.xoff[n + 1];  // second row of the same mode
+        const int64_t i2 = pair ? i + NWV : i;               // (a repeat of row r when unpaired)
+        double acc = 0.0, acc2 = 0.0;
         for (int m = 0; m < a.N; ++m) {
             if (m == n) continue;
             const int len = (int)a.dims[m];
-            const B* rowp = (a.seg_src[n][m] ? bt : blocks) + a.seg_base[n][m] + i * (int64_t)len;
+            const B* base = (a.seg_src[n][m] ? bt : blocks) + a.seg_base[n][m];
+            const B* rowp = base + i * (int64_t)len;
+            const B* rowp2 = base + i2 * (int64_t)len;
             const double* vm = vv + a.xoff[m];
+            // len % E == 0 makes both rows' offsets multiples of 16 bytes
             const bool vec = (len % E == 0) && ((reinterpret_cast<uintptr_t>(rowp) & 15) == 0);
             if (vec) {
                 const VT* rv = reinterpret_cast<const VT*>(rowp);
+                const VT* rv2 = reinterpret_cast<const VT*>(rowp2);
                 const int nv = len / E;
                 for (int q0 = lane; q0 < nv; q0 += 64 * U) {
-                    VT t[U];
+                    VT t[U], t2[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int q = q0 + 64 * u;
-                        t[u] = rv[q < nv ? q : 0];
+                        const int q = q0 + 64 * u < nv ? q0 + 64 * u : 0;
+                        t[u] = rv[q];
+                        t2[u] = rv2[q];
                     }
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int q = q0 + 64 * u;
                         if (q < nv) {
-                            double e[E];
+                            double e[E], e2[E];
                             Vec16<B>::widen(t[u], e);
+                            Vec16<B>::widen(t2[u], e2);
 #pragma unroll
                             for (int c = 0; c < E; ++c) {
                                 const double vj = (COHERENT && !staged) ? ld_ag(vm + q * E + c) : vm[q * E + c];
                                 acc = fma(e[c], vj, acc);
-                                if (want_fro) fro = fma(e[c], e[c], fro);
+                                acc2 = fma(e2[c], vj, acc2);
+                                if (want_fro) {
+                                    fro = fma(e[c], e[c], fro);
+                                    if (pair) fro = fma(e2[c], e2[c], fro);
+                                }
                             }
                         }
                     }
                 }
             } else {
                 for (int j0 = lane; j0 < len; j0 += 64 * U) {
-                    B t[U];
+                    B t[U], t2[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int j = j0 + 64 * u;
-                        t[u] = rowp[j < len ? j : 0];
+                        const int j = j0 + 64 * u < len ? j0 + 64 * u : 0;
+                        t[u] = rowp[j];
+                        t2[u] = rowp2[j];
                     }
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int j = j0 + 64 * u;
                         if (j < len) {
-                            const double e = (double)t[u];
+                            const double e = (double)t[u], e2 = (double)t2[u];
                             const double vj = (COHERENT && !staged) ? ld_ag(vm + j) : vm[j];
                             acc = fma(e, vj, acc);
-                            if (want_fro) fro = fma(e, e, fro);
+                            acc2 = fma(e2, vj, acc2);
+                            if (want_fro) {
+                                fro = fma(e, e, fro);
+                                if (pair) fro = fma(e2, e2, fro);
+                            }
                         }
                     }
                 }
             }
         }
         acc = wave_sum(acc);
-        if (lane == 0) out[r] = acc * scale;
+        acc2 = wave_sum(acc2);
+        if (lane == 0) {
+            out[r] = acc * scale;
+            if (pair) out[r2] = acc2 * scale;
+        }
+        r += pair ? 2 * NWV : NWV;
     }
     return fro;
 }
