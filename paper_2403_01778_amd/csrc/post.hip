@@ -107,6 +107,33 @@ struct Lds {
 // exchanged between workgroups is written and read with device-coherent
 // accesses, so only the workgroup's own ordering is needed after the wait.
 // Waiting is bounded: on timeout the workgroup raises `timeout` and goes on.
+// A grid barrier in two halves: flag_arrive publishes this workgroup's
+// epoch, flag_wait waits until every workgroup has published at least it.
+// Work placed between the two halves overlaps the other workgroups' arrival.
+__device__ void flag_arrive(const PostArgs& a, uint64_t epoch) {
+    __syncthreads();
+    if (a.nwg > 1 && threadIdx.x == 0)
+        __hip_atomic_store(a.flags + blockIdx.x, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void flag_wait(const PostArgs& a, uint64_t epoch, int* timeout) {
+    if (a.nwg == 1) {
+        __syncthreads();
+        return;
+    }
+    for (int w = threadIdx.x; w < a.nwg; w += BS) {
+        unsigned polls = 0;
+        while (__hip_atomic_load(a.flags + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            if (++polls > (1u << 22)) {
+                *timeout = 1;
+                break;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __syncthreads();
+}
+
 __device__ void flag_barrier(const PostArgs& a, uint64_t epoch, int* timeout) {
     __syncthreads();
     if (a.nwg == 1) return;
@@ -641,6 +668,16 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             m = j + 1;
             rho = proj ? a.shift * inv_n1 : L.al[0];
             const bool invariant = beta <= 1e-14 * normJ;
+            // V_{j+1} (own rows) before the convergence check, and the
+            // barrier's arrival half: the check below overlaps the other
+            // workgroups' arrival.  If the check stops the iteration, V_{j+1}
+            // is unused (slot j+1 <= kmax exists) and the wait is skipped;
+            // every workgroup takes the same path, so epochs stay in step.
+            {
+                const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+                for (int64_t r = r_lo + tid; r < r_hi; r += BS) ov.put(j + 1, r, w[r] * ib);
+            }
+            flag_arrive(a, ++sync);
             // an eigen-step almost never converges in one or two Lanczos steps
             // (and a Galerkin solve needs two); checks cost a serial
             // tridiagonal eigensolve, so they start at m = 3
@@ -695,11 +732,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 stop = L.stop != 0;
             }
             HOSCF_ACC(13);
-            if (!stop) {
-                const double ib = 1.0 / beta;
-                for (int64_t r = r_lo + tid; r < r_hi; r += BS) ov.put(j + 1, r, w[r] * ib);
-                flag_barrier(a, ++sync, &L.timeout);
-            }
+            if (!stop) flag_wait(a, sync, &L.timeout);
             HOSCF_ACC(14);
             if (j == 0) HOSCF_MARK(4);
             if (j == 1) HOSCF_MARK(6);

@@ -1,8 +1,9 @@
 """Profiling driver for the post-sweep kernel: runs solves capped at 1, 2, 4
 iterations and prints the phase timings the kernel records in its
 SolveState (device clock at 100 MHz): the epilogue, and per Lanczos step the
-J products, the two reorthogonalisation passes, the convergence checks and the
-new-vector barrier, plus the final normalisation.
+J products, the two reorthogonalisation passes, the next Krylov vector with
+the convergence check (which overlaps the barrier's arrival half) and the
+barrier's remaining wait, plus the final normalisation.
 
   python -m paper_2403_01778_amd.profile_eigen --dims 800,800,800
 """
@@ -47,7 +48,7 @@ def main(argv=None):
         s = [v * 0.01 for v in t[10:15]]
         print(f"dims={dims} eigen-step {it}: lanczos_steps={m} total_us={us(0, 8):.1f} epilogue_us={us(0, 3):.1f} "
               f"per_step_us: J_product={s[0] / max(m - 1, 1):.1f} pass1={s[1] / m:.1f} pass2={s[2] / m:.1f} "
-              f"check={s[3] / m:.1f} new_vector={s[4] / m:.1f} final_us={us(7, 8):.1f}", flush=True)
+              f"new_vector_and_check={s[3] / m:.1f} barrier_wait={s[4] / m:.1f} final_us={us(7, 8):.1f}", flush=True)
     return 0
 
 
