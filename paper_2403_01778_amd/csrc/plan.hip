@@ -45,6 +45,9 @@ void SweepPlan::add_node(int fmt, const void* in, const int* modes, int k, float
     a.P = P;
     a.M = M;
     a.Q = Q;
+    a.Qs = Q;
+    a.qb = 0;
+    a.qc0 = 0;
     a.xp = static_cast<char*>(xa) + map.xoff[s1] * esz;
     a.xq = static_cast<char*>(xa) + map.xoff[sk] * esz;
     a.scale = scale;
@@ -93,7 +96,7 @@ void SweepPlan::add_node(int fmt, const void* in, const int* modes, int k, float
         nd.red.K[nd.nred] = (int)copies;
         ++nd.nred;
     };
-    route(a.doL, nd.sh.nq, P * M, Ldst, a.L);
+    route(a.doL, nd.sh.nq_total(), P * M, Ldst, a.L);
     route(a.doR, nd.sh.npt, M * Q, Rdst, a.R);
     route(a.doC, nd.sh.nmt, P * Q, Cdst, a.C);
     nodes_.push_back(nd);

@@ -10,7 +10,10 @@ namespace hoscf {
 // One launch of the three-output streaming kernel over the view [P, M, Q].
 struct Ttvc3Args {
     const void* T;            // storage-format tensor (or an FP32/FP64 intermediate)
-    int64_t P, M, Q;
+    int64_t P, M, Q;          // Q: the columns this launch part streams
+    int64_t Qs;               // row length of T and of the R / C outputs (>= qb + Q)
+    int64_t qb;               // first column of this part
+    int qc0;                  // first L partial slot of this part
     const void* xp;           // [P] unit factor of the first mode (accumulation type)
     const void* w;            // [M] Kronecker weight of the middle modes
     const void* xq;           // [Q] unit factor of the last mode
@@ -29,7 +32,14 @@ struct Ttvc3Shape {
     int VEC = 1, LR = 64, MB = 16, QW = 64, QWe = 64, NW = 4;
     int nq = 1;
     int64_t nmt = 1, npt = 1, BP = 1;
-    int64_t grid() const { return (int64_t)nq * nmt * npt; }
+    // split: the first Qm columns in nq whole chunks (64 lanes per row), the
+    // Q - Qm remainder columns by ngrp * npt extra workgroups with LR2 lanes
+    // per row, MB2 rows per lane group and one m-tile per wave
+    bool split = false;
+    int64_t Qm = 0, ngrp = 0;
+    int LR2 = 0, MB2 = 0;
+    int nq_total() const { return nq + (split ? 1 : 0); }  // L partial copies
+    int64_t grid() const { return (int64_t)nq * nmt * npt + (split ? ngrp * npt : 0); }
 };
 
 struct ReduceJobs {

@@ -138,10 +138,15 @@ __device__ __forceinline__ void xred(A* v, int lane, int& base) {
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 // ---------------------------------------------------------------------------
-// K1: the three-output streaming kernel.
+// K1: the three-output streaming kernel.  One workgroup tile of the view
+// [P, M, Q'] where Q' = args.Q columns starting at column args.qb of rows of
+// stride args.Qs.  WT (wave tiles): each wave takes one m-tile on its own
+// (the narrow remainder columns of a split sweep), so block (1,N)
+// contributions need no combination across waves: no LDS buffers and no
+// barriers on that path.
 // ---------------------------------------------------------------------------
-template <int FMT, int VEC, int LR, int MB, int NW = 4>
-__global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
+template <int FMT, int VEC, int LR, int MB, int NW, bool WT>
+__device__ __forceinline__ void ttvc3_tile(const Ttvc3Args& args, int64_t bid) {
     using L = Loader<FMT, VEC>;
     using A = typename Fmt<FMT>::A;
     using S = typename Fmt<FMT>::S;
@@ -150,33 +155,33 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     constexpr int WM = G * MB;              // rows of one wave's m-tile
     constexpr int NT = NW * 64;             // threads per workgroup
     constexpr int KS = (32768 / (NT * VEC * (int)sizeof(A))) > 0 ? (32768 / (NT * VEC * (int)sizeof(A))) : 1;
-    __shared__ A cbuf[KS * NW * G * QW];    // = KS * NT * VEC values
+    __shared__ A cbuf[WT ? 1 : KS * NW * G * QW];    // = KS * NT * VEC values
     // Flushes every KS slabs: all waves sum the C contributions into cres,
     // then ONE wave (rotating) writes the combined C rows and the buffered L
     // rows to global memory.  Loads and stores share one completion counter,
     // so only the storing wave waits for its stores; the other waves keep
     // their prefetched slabs in flight.  L values of the workgroup's 4*WM rows
     // are kept per flush (double-buffered) and written as whole rows.
-    constexpr bool LBUF = 2 * KS * NW * WM * (int)sizeof(A) <= 16384;
+    constexpr bool LBUF = !WT && 2 * KS * NW * WM * (int)sizeof(A) <= 16384;
     __shared__ A lbuf[LBUF ? 2 * KS * NW * WM : 1];
-    __shared__ A cres[2 * KS * QW];
+    __shared__ A cres[WT ? 1 : 2 * KS * QW];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: row indices live in SGPRs
     const int g = lane / LR, c = lane % LR;
-    const int64_t P = args.P, M = args.M, Q = args.Q;
-    // Workgroups are dealt round-robin to the 8 XCDs.  Renumber them so that
-    // consecutive tile ids (the q-chunks of the same rows, which share the
-    // cache lines at their edges) run on the same XCD and meet in its L2.
-    int64_t bid = blockIdx.x;
-    {
-        const int64_t G8 = (int64_t)gridDim.x / 8 * 8;
-        if (bid < G8) bid = (bid % 8) * (G8 / 8) + bid / 8;
-    }
+    const int64_t P = args.P, M = args.M, Q = args.Q, Qs = args.Qs;
     const int qc = (int)(bid % args.nq);
     bid /= args.nq;
-    const int64_t mtw = bid % args.nmt;
-    const int64_t pt = bid / args.nmt;
+    int64_t mtw, pt;
+    if constexpr (WT) {
+        const int64_t ngrp = (args.nmt + NW - 1) / NW;
+        mtw = (bid % ngrp) * NW + wave;
+        pt = bid / ngrp;
+        if (mtw >= args.nmt) return;  // no m-tile left for this wave (no barriers on this path)
+    } else {
+        mtw = bid % args.nmt;
+        pt = bid / args.nmt;
+    }
 
     const int64_t q0 = (int64_t)qc * args.QWe + (int64_t)c * VEC;
     const bool qok = (c * VEC < args.QWe) && (q0 < Q);
@@ -185,11 +190,11 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     const int64_t qoff = qok ? (int64_t)c * VEC : 0;
     // m-tiles split M evenly: tile mtw holds rows [mlo, mhi), at most NW * WM
     const int64_t mlo = mtw * M / args.nmt, mhi = (mtw + 1) * M / args.nmt;
-    const int64_t mrow0 = mlo + (int64_t)wave * WM + g;
+    const int64_t mrow0 = mlo + (WT ? 0 : (int64_t)wave * WM) + g;
     const int64_t p0 = pt * args.BP;
     const int64_t p1 = p0 + args.BP < P ? p0 + args.BP : P;
     const A* xp = static_cast<const A*>(args.xp);
-    const A* xq = static_cast<const A*>(args.xq);
+    const A* xq = static_cast<const A*>(args.xq) + args.qb;
     const A* w = static_cast<const A*>(args.w);
     const A scale = A(args.scale);
 
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
     auto ld = [&](int64_t p, int i, int qo) -> typename L::Raw {
         const int64_t m = mrow0 + (int64_t)G * i;
         const int64_t mc = m < mhi ? m : mhi - 1;
-        const typename L::Raw r = L::load(Tb + (p * M + mc) * Q + (int64_t)qc * args.QWe + qo);
+        const typename L::Raw r = L::load(Tb + (p * M + mc) * Qs + args.qb + (int64_t)qc * args.QWe + qo);
         return rok[i] ? r : L::zero();
     };
     auto body = [&](auto refill, typename L::Raw* raw, int64_t p) {
@@ -269,11 +274,25 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
                         lbuf[(par * KS + slot) * NW * WM + wave * WM + rl] = dl[j];
                     } else {
                         const int64_t m = mrow0 - g + rl;
-                        if (m < mhi) Lout[((int64_t)qc * P + p) * M + m] = dl[j] * scale;
+                        if (m < mhi) Lout[((int64_t)(args.qc0 + qc) * P + p) * M + m] = dl[j] * scale;
                     }
                 }
             }
         }
+        if constexpr (WT) {
+            if (args.doC) {
+                // sum over the wave's row groups (lanes of equal c), fixed order
+#pragma unroll
+                for (int sft = LR; sft < 64; sft <<= 1)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) accC[v] += __shfl_xor(accC[v], sft);
+                if (g == 0 && qok) {
+                    A* dstc = Cout + (mtw * P + p) * Qs + args.qb + q0;
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) dstc[v] = accC[v] * scale;
+                }
+            }
+        } else {
         if (args.doC) {
             A* dst = cbuf + ((slot * NW + wave) * G + g) * QW + c * VEC;
 #pragma unroll
@@ -302,7 +321,7 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
                             const int64_t q = (int64_t)qc * args.QWe + qi;
                             const int64_t pp = p - slot + 1 + s;
                             if (qi < args.QWe && q < Q)
-                                __builtin_nontemporal_store(cres[par * KS * QW + idx], Cout + (mtw * P + pp) * Q + q);
+                                __builtin_nontemporal_store(cres[par * KS * QW + idx], Cout + (mtw * P + pp) * Qs + args.qb + q);
                         }
                     }
                     if constexpr (LBUF) {
@@ -312,7 +331,7 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
                                 const int s = idx / (NW * WM), k = idx - s * (NW * WM);
                                 const int64_t m = mlo + k;
                                 const int64_t pp = p - slot + 1 + s;
-                                if (m < mhi) Lout[((int64_t)qc * P + pp) * M + m] = lbuf[par * KS * NW * WM + idx] * scale;
+                                if (m < mhi) Lout[((int64_t)(args.qc0 + qc) * P + pp) * M + m] = lbuf[par * KS * NW * WM + idx] * scale;
                             }
                         }
                     }
@@ -321,6 +340,7 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
                 par ^= 1;
                 slot = 0;
             }
+        }
         }
     };
     // One register buffer refilled row by row: MB - 1 to MB rows of loads
@@ -345,11 +365,37 @@ __global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
         for (int i = 0; i < MB; ++i) {
             if (!rok[i]) continue;
             const int64_t m = mrow0 + (int64_t)G * i;
-            A* dst = Rout + (pt * M + m) * Q + q0;
+            A* dst = Rout + (pt * M + m) * Qs + args.qb + q0;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) dst[v] = accR[i][v] * scale;
         }
     }
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs.  Renumber them so that
+// consecutive tile ids (the q-chunks of the same rows, which share the cache
+// lines at their edges) run on the same XCD and meet in its L2.
+__device__ __forceinline__ int64_t xcd_bid() {
+    int64_t bid = blockIdx.x;
+    const int64_t G8 = (int64_t)gridDim.x / 8 * 8;
+    if (bid < G8) bid = (bid % 8) * (G8 / 8) + bid / 8;
+    return bid;
+}
+
+template <int FMT, int VEC, int LR, int MB, int NW = 4>
+__global__ __launch_bounds__(NW * 64) void ttvc3_kernel(Ttvc3Args args) {
+    ttvc3_tile<FMT, VEC, LR, MB, NW, false>(args, xcd_bid());
+}
+
+// A split sweep in one launch: the first `ga` workgroups stream the whole
+// 64-lane chunks of the last mode (8 waves per workgroup), the rest stream
+// the narrow remainder columns with LR2 lanes per row and one m-tile per
+// wave, so that every load instruction has all its lanes busy.
+template <int FMT, int VEC, int MB, int LR2, int MB2>
+__global__ __launch_bounds__(512) void ttvc3_split_kernel(Ttvc3Args main, Ttvc3Args rem, int64_t ga) {
+    const int64_t bid = xcd_bid();
+    if (bid < ga) ttvc3_tile<FMT, VEC, 64, MB, 8, false>(main, bid);
+    else ttvc3_tile<FMT, VEC, LR2, MB2, 8, true>(rem, bid - ga);
 }
 
 // ---------------------------------------------------------------------------
@@ -501,8 +547,29 @@ static const void* k1_instance(const Ttvc3Shape& sh) {
     return (const void*)&ttvc3_kernel<FMT, 1, 64, 16>;
 }
 
+// The split instance: remainder lanes per row LR2 (4 or 8), rows per lane
+// group MB2 = MB * LR2 / 8, so one wave covers a whole m-tile.
+template <int FMT>
+static const void* k1_split(const Ttvc3Shape& sh) {
+    constexpr int V = Fmt<FMT>::VEC;
+    constexpr int MBV = mb_vec<FMT>();
+    if (sh.VEC != V || sh.MB != MBV || sh.NW != 8) return nullptr;
+    if (sh.LR2 == 8) return (const void*)&ttvc3_split_kernel<FMT, V, MBV, 8, MBV>;
+    if (sh.LR2 == 4) return (const void*)&ttvc3_split_kernel<FMT, V, MBV, 4, MBV / 2>;
+    return nullptr;
+}
+
 // The kernel a shape launches (block: NW waves); nullptr if not instantiated.
 static const void* k1_fn(int fmt, const Ttvc3Shape& sh) {
+    if (sh.split) {
+        switch (fmt) {
+            case HOSCF_F64: return k1_split<HOSCF_F64>(sh);
+            case HOSCF_F32: return k1_split<HOSCF_F32>(sh);
+            case HOSCF_BF16: return k1_split<HOSCF_BF16>(sh);
+            case HOSCF_FP8E4M3: return k1_split<HOSCF_FP8E4M3>(sh);
+        }
+        return nullptr;
+    }
     switch (fmt) {
         case HOSCF_F64: return k1_instance<HOSCF_F64>(sh);
         case HOSCF_F32: return k1_instance<HOSCF_F32>(sh);
@@ -547,6 +614,21 @@ Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, const SweepTuni
     const int G = 64 / s.LR;
     s.QW = s.LR * s.VEC;
     s.nq = (int)((Q + s.QW - 1) / s.QW);
+    // Split sweep: when whole 64-lane chunks leave a remainder of at most 8
+    // vectors, the remainder goes to extra workgroups in the same launch with
+    // 4 or 8 lanes per row (all lanes busy) instead of a ragged 64-lane chunk.
+    {
+        const int64_t Qr = Q % s.QW;
+        const int lr2 = Qr > 0 ? pow2_at_least((Qr + s.VEC - 1) / s.VEC) : 0;
+        if (s.VEC > 1 && s.LR == 64 && s.NW == 8 && s.MB == mbs[fmt] && tune.align && Q > s.QW &&
+            (lr2 == 4 || lr2 == 8)) {
+            s.split = true;
+            s.Qm = Q - Qr;
+            s.LR2 = lr2;
+            s.MB2 = s.MB * lr2 / 8;
+            s.nq = (int)(s.Qm / s.QW);
+        }
+    }
     if (tune.align || s.nq == 1) {
         // chunks of QW elements (whole cache lines when QW * esz is a multiple
         // of 128 bytes); the last chunk is ragged
@@ -559,7 +641,8 @@ Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, const SweepTuni
     const int64_t wm = (int64_t)G * s.MB;
     const int64_t nmt_w = (M + wm - 1) / wm;
     s.nmt = (nmt_w + s.NW - 1) / s.NW;
-    const int64_t cols = (int64_t)s.nq * s.nmt;
+    if (s.split) s.ngrp = (s.nmt + s.NW - 1) / s.NW;
+    const int64_t cols = (int64_t)s.nq * s.nmt + (s.split ? s.ngrp : 0);
     // p-split: balance rounds of resident workgroups against the R partials it
     // creates (npt copies of M x Q accumulators, written and read back).
     const int64_t slots = target_wg > 0 ? target_wg : std::max<int64_t>(1, resident_slots(fmt, s));
@@ -590,8 +673,20 @@ Ttvc3Shape ttvc3_shape(int fmt, int64_t P, int64_t M, int64_t Q, const SweepTuni
 hipError_t launch_ttvc3(int fmt, const Ttvc3Shape& sh, const Ttvc3Args& a, hipStream_t s) {
     const void* fn = k1_fn(fmt, sh);
     if (!fn) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((int64_t)sh.nq * sh.nmt * sh.npt));
-    void* kargs[] = {const_cast<Ttvc3Args*>(&a)};
+    const dim3 grid((unsigned)sh.grid());
+    if (!sh.split) {
+        void* kargs[] = {const_cast<Ttvc3Args*>(&a)};
+        return hipLaunchKernel(fn, grid, dim3(sh.NW * 64), kargs, 0, s);
+    }
+    Ttvc3Args m = a, r = a;
+    m.Q = sh.Qm;
+    r.Q = a.Q - sh.Qm;
+    r.qb = sh.Qm;
+    r.qc0 = sh.nq;
+    r.nq = 1;
+    r.QWe = (int)r.Q;
+    int64_t ga = (int64_t)sh.nq * sh.nmt * sh.npt;
+    void* kargs[] = {&m, &r, &ga};
     return hipLaunchKernel(fn, grid, dim3(sh.NW * 64), kargs, 0, s);
 }
 

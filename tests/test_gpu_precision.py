@@ -78,7 +78,8 @@ def _lowprec_case(lib, dims, fmt, seed):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
-@pytest.mark.parametrize("dims", [(37, 29, 64), (37, 29, 23), (9, 10, 11, 16), (6, 7, 5, 4, 32), (40, 48)])
+@pytest.mark.parametrize("dims", [(37, 29, 64), (37, 29, 23), (9, 10, 11, 16), (6, 7, 5, 4, 32), (40, 48),
+                                  (10, 20, 576), (6, 10, 1152), (6, 10, 1088)])  # split sweeps
 def test_ttvc_lowprec_parity(lib, fmt, dims):
     print(f"[ttvc-lp] fmt={fmt} dims={dims}", flush=True)
     _, Tq, scale, Tdeq = _lowprec_case(lib, dims, fmt, 100 + sum(dims))

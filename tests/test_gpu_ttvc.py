@@ -56,7 +56,12 @@ def _check_against_oracle(lib, Tt, x, scale=1.0, Tstored=None):
 
 @pytest.mark.parametrize("dims", [(37, 29, 23), (130, 257, 300), (64, 64, 64), (3, 5, 7), (1, 1, 1), (2, 1, 3),
                                   (10, 10, 7), (5, 300, 2), (257, 3, 1000), (90, 70, 801), (1, 50, 60),
-                                  (50, 60, 1), (600, 2, 2)])
+                                  (50, 60, 1), (600, 2, 2),
+                                  # split sweeps (whole 64-lane chunks + a narrow remainder):
+                                  # FP32 288 and 544 (8 lanes), 272 (4 lanes), FP64 272 and
+                                  # 136; 2000 middle rows give two wave-tile groups
+                                  (40, 30, 288), (20, 300, 544), (30, 20, 272), (30, 20, 136),
+                                  (3, 2000, 288)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_ttvc_order3(lib, dims, dtype):
     Tt, x = _case(dims, dtype, 1000 + sum(dims))
@@ -88,7 +93,7 @@ def _check_outputs(Tnp, x, flat, g, tol):
     assert np.all(np.abs(g.cpu().numpy() - g_ref) <= tol * g_abs + 1e-300)
 
 
-@pytest.mark.parametrize("dims", [(70, 90, 300), (20, 24, 28, 256), (9, 10, 11, 12, 64)])
+@pytest.mark.parametrize("dims", [(70, 90, 300), (60, 70, 288), (20, 24, 28, 256), (9, 10, 11, 12, 64)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_ttvc_every_tiling(lib, dims, dtype):
     """Every tiling the autotuner may choose (lanes per row, rows per lane
