@@ -45,8 +45,8 @@ HBM_PEAK_GBPS = 8000.0
 # factors a 1 GiB device copy reads on the same counters); summary in
 # profiles/ttvc3_kernel_800cubed_f32_pmc.md.  Valid only for the kernel source
 # the counters were taken on.
-TRAFFIC = {"kernel_source_sha256": "fc9f19a72b18a63c8af78aae8008daafe9765c19b493883e1b58483d615b9a01",
-           "read_bytes": 2_004_326.1 * 1024, "write_bytes": 50_093.8 * 1024}
+TRAFFIC = {"kernel_source_sha256": "0ae1db0b54d03cae1835b70b52dccfbd87324840542a9877225929dd7d60ba40",
+           "read_bytes": 2_007_698.1 * 1024, "write_bytes": 55_060.9 * 1024}
 
 
 def measured_traffic():
@@ -322,7 +322,7 @@ def main():
         "ttvc_kernels_ms": round(ms_k1, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(),
-                     "kernel": "ttvc3_kernel (level-1 pass over T)", "bytes_per_launch": nbytes,
+                     "kernel": "level-1 TTVc launch over T (ttvc3_split_kernel for this shape)", "bytes_per_launch": nbytes,
                      "launch_ms": round(ms_root, 5)},
     }
     if not args.no_extras:
