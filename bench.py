@@ -207,8 +207,9 @@ def leg_backward(hoscf, synth, items=4):
         opts = hoscf.options(algo="hoscf", tol=1e-6, max_iter=300)
         hoscf.solve_raw(Td, x0, opts)
         dt_s, (sig, x, _) = _timed(lambda: hoscf.solve_raw(Td, x0, opts), 1)
-        hoscf.backward(Td, x, sig, 1.0, w)
-        dt_b, (g, mu, info) = _timed(lambda: hoscf.backward(Td, x, sig, 1.0, w, return_info=True), 3)
+        for _ in range(2):  # warm-up: first-call allocations and cache state
+            hoscf.backward(Td, x, sig, 1.0, w)
+        dt_b, (g, mu, info) = _timed(lambda: hoscf.backward(Td, x, sig, 1.0, w, return_info=True), 5)
         t_solve += dt_s
         t_bwd += dt_b
         steps.append(info[0])
