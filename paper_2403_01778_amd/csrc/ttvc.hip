@@ -12,14 +12,18 @@
 // L and R (orders N-1), which are small and cache-resident.
 //
 // Layout of the work: lanes own 16-byte vectors of consecutive q (VEC
-// elements), LR lanes per row, G = 64/LR rows per wave instruction.  A wave
-// holds R for its MB rows per group in registers while it streams over a
-// p-range, refilling each row's load registers with the next slab's row as
-// soon as the row is consumed (MB - 1 to MB rows stay in flight with one
-// buffer, which leaves room for twice the rows per workgroup), flushes C once per p (the four waves of a workgroup share the
-// q-chunk and p-range and combine their C contributions in LDS, in a fixed
-// order), and reduces L per row with a transposed butterfly over its lanes.
-// Every reduction has a fixed order, so a sweep is bitwise reproducible.
+// elements), LR lanes per row, G = 64/LR rows per wave instruction.  A
+// workgroup owns a q-chunk, an m-tile (M split evenly into tiles) and a
+// p-range.  A wave holds R for its MB rows per group in registers while it
+// streams over the p-range, refilling each row's load registers with the next
+// slab's row as soon as the row is consumed (MB - 1 to MB rows stay in flight
+// with one buffer, which leaves room for twice the rows per workgroup).  The
+// waves of a workgroup combine their C contributions in LDS every KS slabs,
+// in a fixed order, and L is reduced per row with a transposed butterfly over
+// the row's lanes.  When the last extent leaves a narrow remainder after the
+// whole 64-lane chunks, a split launch streams the remainder with a few lanes
+// per row and one m-tile per wave (ttvc3_split_kernel).  Every reduction has
+// a fixed order, so a sweep is bitwise reproducible.
 #include "common.h"
 #include "ttvc.h"
 

@@ -131,8 +131,9 @@ def test_tune_table_register(lib):
         lib.tune_set(lib.F32, dims, (0, 1, 12, 1, 8, 8))
 
 
-def test_ttvc_deterministic(lib):
-    Tt, x = _case((150, 140, 270), torch.float32, 7)
+@pytest.mark.parametrize("dims", [(150, 140, 270), (40, 300, 544)])  # the second is a split sweep
+def test_ttvc_deterministic(lib, dims):
+    Tt, x = _case(dims, torch.float32, 7)
     T = Tt.to(DEV)
     a = lib.ttvc(T, torch.from_numpy(x))
     b = lib.ttvc(T, torch.from_numpy(x))
