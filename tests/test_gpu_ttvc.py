@@ -69,7 +69,9 @@ def test_ttvc_order3(lib, dims, dtype):
 
 
 @pytest.mark.parametrize("dims", [(9, 10, 11, 12), (5, 6, 7, 4, 8), (4, 3, 5, 2, 3, 4), (17, 33), (3,) * 8,
-                                  (2, 70, 3, 65), (33, 1, 40, 2)])
+                                  (2, 70, 3, 65), (33, 1, 40, 2),
+                                  # split sweeps at level 1 and in the recursion on R
+                                  (6, 5, 7, 288), (3, 4, 5, 6, 544)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_ttvc_order_n(lib, dims, dtype):
     Tt, x = _case(dims, dtype, 2000 + sum(dims))
