@@ -419,6 +419,47 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(ReduceJobs jobs) {
     }
 }
 
+// K2 for many partials (K in the hundreds: the block (1,N) partials of one
+// m-tile each when M is large).  A workgroup owns 64 consecutive entries;
+// wave w sums partials k = w, w + 16, w + 32, ... in increasing k, four loads
+// in flight per lane, and wave 0 adds the 16 wave sums in wave order.  The
+// order is fixed, so the result is bitwise reproducible.
+template <typename A>
+__global__ __launch_bounds__(1024) void reduce_parts_wide_kernel(ReduceJobs jobs) {
+    __shared__ double part[16][64];
+    const int j = blockIdx.y;
+    const int64_t n = jobs.n[j];
+    const int K = jobs.K[j];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    if (i0 >= n) return;  // the whole workgroup: no barrier is left unmatched
+    const A* src = static_cast<const A*>(jobs.src[j]);
+    A* dst = static_cast<A*>(jobs.dst[j]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = i0 + lane;
+    const bool ok = i < n;
+    const int64_t ic = ok ? i : i0;  // lanes past n read an entry in range; their sum is not stored
+    double sum = 0.0;
+    int k = wave;
+    for (; k + 48 < K; k += 64) {
+        const A t0 = src[(int64_t)k * n + ic];
+        const A t1 = src[(int64_t)(k + 16) * n + ic];
+        const A t2 = src[(int64_t)(k + 32) * n + ic];
+        const A t3 = src[(int64_t)(k + 48) * n + ic];
+        sum += (double)t0;
+        sum += (double)t1;
+        sum += (double)t2;
+        sum += (double)t3;
+    }
+    for (; k < K; k += 16) sum += (double)src[(int64_t)k * n + ic];
+    part[wave][lane] = sum;
+    __syncthreads();
+    if (wave == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += part[w][lane];
+        if (ok) dst[i] = A(t);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Factor preparation: unit blocks (eq. factor) in FP64 and in the sweep's
 // accumulation type; flags a zero or non-finite block.
@@ -699,14 +740,39 @@ hipError_t launch_ttvc3(int fmt, const Ttvc3Shape& sh, const Ttvc3Args& a, hipSt
 }
 
 hipError_t launch_reduce(bool f64, const ReduceJobs& jobs, int njobs, hipStream_t s) {
-    if (njobs == 0) return hipSuccess;
-    int64_t nmax = 0;
-    for (int j = 0; j < njobs; ++j) nmax = std::max(nmax, jobs.n[j]);
-    int64_t blocks = std::min<int64_t>((nmax + 255) / 256, 4096);
-    dim3 grid((unsigned)std::max<int64_t>(blocks, 1), njobs);
-    if (f64) hipLaunchKernelGGL(reduce_parts_kernel<double>, grid, dim3(256), 0, s, jobs);
-    else hipLaunchKernelGGL(reduce_parts_kernel<float>, grid, dim3(256), 0, s, jobs);
-    return hipGetLastError();
+    // jobs with few partials: one thread per entry sums them in order; jobs
+    // with many: the wide kernel splits the partials over 16 waves
+    constexpr int kWide = 32;
+    ReduceJobs narrow{}, wide{};
+    int nn = 0, nw = 0;
+    int64_t nmax_n = 0, nmax_w = 0;
+    for (int j = 0; j < njobs; ++j) {
+        ReduceJobs& d = jobs.K[j] > kWide ? wide : narrow;
+        int& c = jobs.K[j] > kWide ? nw : nn;
+        d.src[c] = jobs.src[j];
+        d.dst[c] = jobs.dst[j];
+        d.n[c] = jobs.n[j];
+        d.K[c] = jobs.K[j];
+        ++c;
+        if (jobs.K[j] > kWide) nmax_w = std::max(nmax_w, jobs.n[j]);
+        else nmax_n = std::max(nmax_n, jobs.n[j]);
+    }
+    if (nn > 0) {
+        const int64_t blocks = std::min<int64_t>((nmax_n + 255) / 256, 4096);
+        const dim3 grid((unsigned)std::max<int64_t>(blocks, 1), nn);
+        if (f64) hipLaunchKernelGGL(reduce_parts_kernel<double>, grid, dim3(256), 0, s, narrow);
+        else hipLaunchKernelGGL(reduce_parts_kernel<float>, grid, dim3(256), 0, s, narrow);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (nw > 0) {
+        const dim3 grid((unsigned)std::max<int64_t>((nmax_w + 63) / 64, 1), nw);
+        if (f64) hipLaunchKernelGGL(reduce_parts_wide_kernel<double>, grid, dim3(1024), 0, s, wide);
+        else hipLaunchKernelGGL(reduce_parts_wide_kernel<float>, grid, dim3(1024), 0, s, wide);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_prep(bool f64, const double* x, int N, const FactorOffsets& off, double* xu, void* xa,

@@ -61,7 +61,9 @@ def _check_against_oracle(lib, Tt, x, scale=1.0, Tstored=None):
                                   # FP32 288 and 544 (8 lanes), 272 (4 lanes), FP64 272 and
                                   # 136; 2000 middle rows give two wave-tile groups
                                   (40, 30, 288), (20, 300, 544), (30, 20, 272), (30, 20, 136),
-                                  (3, 2000, 288)])
+                                  (3, 2000, 288),
+                                  # 40 m-tiles: the block (1,3) partials take the wide reduction
+                                  (2, 20000, 64)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_ttvc_order3(lib, dims, dtype):
     Tt, x = _case(dims, dtype, 1000 + sum(dims))
