@@ -95,7 +95,8 @@ __device__ double block_sum(double v, double* red) {
 
 // sum_t a[t * stride] * v[t] for t < n in FP64, four independent partial
 // sums (t mod 4) so consecutive FMAs do not wait on each other.
-__device__ __forceinline__ double dot4(const float* a, int stride, const double* v, int n) {
+template <typename PA, typename PV>
+__device__ __forceinline__ double dot4(PA a, int stride, PV v, int n) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int t = 0;
     for (; t + 3 < n; t += 4) {
@@ -147,15 +148,27 @@ template <> struct SlabVec<4> { typedef f32x4 T; };
 template <int BT, int VEC>
 __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& item, int r, int D) {
     using LT = typename SlabVec<VEC>::T;
+    typedef __attribute__((address_space(3))) LT lds_lt;
+    typedef const __attribute__((address_space(1))) LT glb_lt;
+    typedef const __attribute__((address_space(1))) double glb_f64;
     constexpr int QV = (kSlabFloats / VEC + BT - 1) / BT;
     constexpr int RMAX = kBatchMaxR;
     const int tid = threadIdx.x;
     const int I1 = item.I[0], I2 = item.I[1], I3 = item.I[2];
     const int n23 = I2 * I3, nv = n23 / VEC;
-    float* A12 = L.blk;
-    float* A13 = A12 + I1 * I2;
-    float* A23 = A13 + I1 * I3;
-    const LT* Tv = reinterpret_cast<const LT*>(item.T);
+    // LDS-typed views of the parts of L this loop touches (L itself arrives
+    // as a generic reference)
+    lds_f32* A12 = as_lds(L.blk);
+    lds_f32* A13 = A12 + I1 * I2;
+    lds_f32* A23 = A13 + I1 * I3;
+    lds_f32* slab = as_lds(L.a.slab);
+    const lds_f64* lu = as_lds(L.u);
+    lds_f64* lxi = as_lds(L.xi);
+    const lds_f64* ldefl = as_lds(L.defl);
+    // the tensor and the earlier terms' factors: global memory (typed, as
+    // they arrive through references)
+    glb_lt* Tv = (glb_lt*)item.T;
+    glb_f64* xall = (glb_f64*)(a.x_out + item.xoff);
     // deflation: row threads keep their fixed factor entries of the earlier
     // terms (x_{s,2}[j] for A12 rows, x_{s,3}[k] for A13 rows) and thread t
     // keeps x_{s,1}[t], published to LDS when slab t is processed
@@ -164,7 +177,7 @@ __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& 
         const int col = tid < I2 ? I1 + tid : (tid >= BT / 2 && tid < BT / 2 + I3 ? I1 + I2 + tid - BT / 2 : -1);
 #pragma unroll
         for (int s2 = 0; s2 < RMAX; ++s2) {
-            const double* xs = a.x_out + item.xoff + (int64_t)s2 * D;
+            glb_f64* xs = xall + (int64_t)s2 * D;
             cfix[s2] = (s2 < r && col >= 0) ? xs[col] : 0.0;
             x1r[s2] = (s2 < r && tid < I1) ? xs[tid] : 0.0;
         }
@@ -181,7 +194,7 @@ __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& 
     // in registers).
 #define BATCH_LOAD(B, I)                                      \
     {                                                         \
-        const LT* S_ = Tv + (int64_t)(I) * nv;                 \
+        glb_lt* S_ = Tv + (int64_t)(I) * nv;                  \
         _Pragma("unroll") for (int q = 0; q < QV; ++q) {      \
             const int e = tid + q * BT;                       \
             B[q] = S_[e < nv ? e : 0];                        \
@@ -194,10 +207,10 @@ __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& 
         if (live) {                                                                              \
             _Pragma("unroll") for (int q = 0; q < QV; ++q) {                                     \
                 const int e = tid + q * BT;                                                      \
-                if (e < nv) *reinterpret_cast<LT*>(L.a.slab + e * VEC) = CUR[q];                 \
+                if (e < nv) *reinterpret_cast<lds_lt*>(slab + e * VEC) = CUR[q];                 \
             }                                                                                    \
             if (tid == i_)                                                                       \
-                _Pragma("unroll") for (int s2 = 0; s2 < RMAX; ++s2) if (s2 < r) L.xi[s2] = x1r[s2]; \
+                _Pragma("unroll") for (int s2 = 0; s2 < RMAX; ++s2) if (s2 < r) lxi[s2] = x1r[s2];  \
         }                                                                                        \
         BATCH_LOAD(LD, i_ + 2 < I1 ? i_ + 2 : I1 - 1)                                             \
         __syncthreads();                                                                         \
@@ -205,7 +218,7 @@ __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& 
         __syncthreads();                                                                         \
     }
     auto slab_rows = [&](const LT* cur, int i) {
-        const double u1i = L.u[i];
+        const double u1i = lu[i];
 #pragma unroll
         for (int q = 0; q < QV; ++q) {
             if constexpr (VEC == 1) {
@@ -218,21 +231,21 @@ __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& 
         // row i of A12 (threads 0..I2-1) and of A13 (threads BT/2..BT/2+I3-1)
         if (tid < I2) {
             const int j = tid;
-            const double s = dot4(L.a.slab + j * I3, 1, L.u + I1 + I2, I3);
+            const double s = dot4(slab + j * I3, 1, lu + I1 + I2, I3);
             double corr = 0.0;
 #pragma unroll
             for (int s2 = 0; s2 < RMAX; ++s2)
-                if (s2 < r) corr = fma(L.defl[3 * s2 + 0] * L.xi[s2], cfix[s2], corr);
+                if (s2 < r) corr = fma(ldefl[3 * s2 + 0] * lxi[s2], cfix[s2], corr);
             const float v = (float)(s - corr);
             A12[i * I2 + j] = v;
             fro = fma((double)v, (double)v, fro);
         } else if (tid >= BT / 2 && tid < BT / 2 + I3) {
             const int k = tid - BT / 2;
-            const double s = dot4(L.a.slab + k, I3, L.u + I1, I2);
+            const double s = dot4(slab + k, I3, lu + I1, I2);
             double corr = 0.0;
 #pragma unroll
             for (int s2 = 0; s2 < RMAX; ++s2)
-                if (s2 < r) corr = fma(L.defl[3 * s2 + 1] * L.xi[s2], cfix[s2], corr);
+                if (s2 < r) corr = fma(ldefl[3 * s2 + 1] * lxi[s2], cfix[s2], corr);
             const float v = (float)(s - corr);
             A13[i * I3 + k] = v;
             fro = fma((double)v, (double)v, fro);
@@ -258,8 +271,8 @@ __device__ double batch_sweep(const BatchArgs& a, BatchLds& L, const BatchItem& 
                 const int j = f / I3, k = f - j * I3;
                 double corr = 0.0;
                 for (int s2 = 0; s2 < r; ++s2) {
-                    const double* xs = a.x_out + item.xoff + (int64_t)s2 * D;
-                    corr = fma(L.defl[3 * s2 + 2] * xs[I1 + j], xs[I1 + I2 + k], corr);
+                    glb_f64* xs = xall + (int64_t)s2 * D;
+                    corr = fma(ldefl[3 * s2 + 2] * xs[I1 + j], xs[I1 + I2 + k], corr);
                 }
                 const float v = (float)(acc[q][c] - corr);
                 A23[f] = v;

@@ -21,6 +21,20 @@ constexpr int kMaxBlocks = kMaxOrder * (kMaxOrder - 1) / 2;
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
+// Pointers into LDS carry the LDS address space, so that accesses through
+// them compile to ds_read / ds_write.  Through a generic pointer (a reference
+// to an LDS struct passed to a function that is not inlined, or a pointer that
+// may address either LDS or global memory) the compiler emits flat accesses,
+// which count against both the LDS and the vector-memory counters: every use
+// of such a value then also waits for all outstanding global loads, which
+// serialises the memory pipeline of the loop around it.
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) float lds_f32;
+__device__ __forceinline__ lds_f64* as_lds(double* p) { return (lds_f64*)p; }
+__device__ __forceinline__ const lds_f64* as_lds(const double* p) { return (const lds_f64*)p; }
+__device__ __forceinline__ lds_f32* as_lds(float* p) { return (lds_f32*)p; }
+__device__ __forceinline__ const lds_f32* as_lds(const float* p) { return (const lds_f32*)p; }
+
 // Bump allocator over a caller workspace.  With a NULL base it only measures;
 // `ok` drops to false when the capacity is exceeded.
 struct Arena {

@@ -36,7 +36,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum over the workgroup (256 threads); every thread receives the total.
-__device__ double wg_sum(double v, double* lds_w) {
+__device__ __forceinline__ double wg_sum(double v, lds_f64* lds_w) {
     v = wave_sum(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) lds_w[threadIdx.x >> 6] = v;
@@ -93,30 +93,51 @@ struct Lds {
     double part[BS];
     int64_t xoff[kMaxOrder + 1];
     double fl[kMaxOrder], inv[kMaxOrder];
+    uint64_t swp[kKmaxLds / 64];  // row swaps of the tridiagonal factorisation
     double theta, ritz;
+    double hint_lo, hint_hi;  // extreme eigenvalues at the previous check of this Lanczos run
     uint64_t epoch0;
-    int stop, ok, timeout;
+    int stop, ok, timeout, hinted;
 };
 
 // Grid-wide synchronisation point number `epoch` of a co-resident grid: each
-// workgroup publishes `epoch` in its own flag (release, after the workgroup
-// barrier has retired its stores) and then waits until every flag has
-// reached it.  Flags only grow (epochs continue across launches through
-// SolveState::epoch), so no flag is ever reset inside a launch and a fast
-// workgroup that publishes the next epoch early cannot be missed.  Data
-// exchanged between workgroups is written and read with device-coherent
-// accesses, so only the workgroup's own ordering is needed after the wait.
-// Waiting is bounded: on timeout the workgroup raises `timeout` and goes on.
+// workgroup publishes `epoch` in its own flag once its stores have completed,
+// and then waits until every flag has reached it.  Flags only grow (epochs
+// continue across launches through SolveState::epoch), so no flag is ever
+// reset inside a launch and a fast workgroup that publishes the next epoch
+// early cannot be missed.  Waiting is bounded: on timeout the workgroup
+// raises `timeout` and goes on.
+//
+// Data exchanged between workgroups is written and read with agent-scope
+// accesses (stores write through the XCD's L2, loads fetch the coherent
+// copy), so a store is visible to every workgroup once it has completed and
+// no cache maintenance is needed on either side.  To publish, each wave
+// completes its own outstanding stores (the wait is also a compiler barrier),
+// the workgroup barrier orders all of them before thread 0, and thread 0
+// stores the epoch with a relaxed agent-scope store.  An agent-scope release
+// store would in addition write back every dirty line of the XCD's L2 (which
+// only plain stores leave, and nothing exchanged here is one), at a cost of
+// microseconds per barrier.
+__device__ __forceinline__ void complete_stores() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+__device__ __forceinline__ void publish_epoch(const PostArgs& a, uint64_t epoch) {
+    complete_stores();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(a.flags + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // A grid barrier in two halves: flag_arrive publishes this workgroup's
 // epoch, flag_wait waits until every workgroup has published at least it.
 // Work placed between the two halves overlaps the other workgroups' arrival.
-__device__ void flag_arrive(const PostArgs& a, uint64_t epoch) {
-    __syncthreads();
-    if (a.nwg > 1 && threadIdx.x == 0)
-        __hip_atomic_store(a.flags + blockIdx.x, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void flag_arrive(const PostArgs& a, uint64_t epoch) {
+    if (a.nwg > 1) publish_epoch(a, epoch);
+    else __syncthreads();
 }
 
-__device__ void flag_wait(const PostArgs& a, uint64_t epoch, int* timeout) {
+__device__ __forceinline__ void flag_wait(const PostArgs& a, uint64_t epoch, int* timeout) {
     if (a.nwg == 1) {
         __syncthreads();
         return;
@@ -134,10 +155,12 @@ __device__ void flag_wait(const PostArgs& a, uint64_t epoch, int* timeout) {
     __syncthreads();
 }
 
-__device__ void flag_barrier(const PostArgs& a, uint64_t epoch, int* timeout) {
-    __syncthreads();
-    if (a.nwg == 1) return;
-    if (threadIdx.x == 0) __hip_atomic_store(a.flags + blockIdx.x, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void flag_barrier(const PostArgs& a, uint64_t epoch, int* timeout) {
+    if (a.nwg == 1) {
+        __syncthreads();
+        return;
+    }
+    publish_epoch(a, epoch);
     for (int w = threadIdx.x; w < a.nwg; w += BS) {
         unsigned polls = 0;
         while (__hip_atomic_load(a.flags + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
@@ -157,7 +180,7 @@ __device__ void flag_barrier(const PostArgs& a, uint64_t epoch, int* timeout) {
 // reading).  After the barrier every thread gathers partials with eight loads
 // in flight into LDS (`stage`, kVecLds doubles), then thread k sums column k
 // over the workgroups in workgroup order.  Totals land in L.hsum.
-__device__ void allreduce(const PostArgs& a, int K, int& parity, uint64_t& sync, Lds& L, double* stage) {
+__device__ __forceinline__ void allreduce(const PostArgs& a, int K, int& parity, uint64_t& sync, Lds& L, lds_f64* stage) {
     if (a.nwg == 1) {
         __syncthreads();
         for (int k = threadIdx.x; k < K; k += BS) L.hsum[k] = L.mine[k];
@@ -200,15 +223,15 @@ __device__ void allreduce(const PostArgs& a, int K, int& parity, uint64_t& sync,
 
 // Per-thread partial dot products of own rows, summed over the workgroup
 // into L.mine[k].
-__device__ void wg_to_mine(double v, int k, Lds& L) {
-    v = wg_sum(v, L.red4);
+__device__ __forceinline__ void wg_to_mine(double v, int k, Lds& L) {
+    v = wg_sum(v, as_lds(L.red4));
     if (threadIdx.x == 0) L.mine[k] = v;
 }
 
 // Copy n doubles from global memory into LDS with eight loads per thread in
 // flight (indices clamped, stores masked).
 template <bool COHERENT>
-__device__ void stage_to_lds(double* dst, const double* src, int64_t n) {
+__device__ __forceinline__ void stage_to_lds(lds_f64* dst, const double* src, int64_t n) {
     for (int64_t b = threadIdx.x; b < n; b += 8 * BS) {
         double t[8];
 #pragma unroll
@@ -240,18 +263,72 @@ struct Vec16<double> {
     __device__ static void widen(T v, double* o) { o[0] = v.x; o[1] = v.y; }
 };
 
+// The 16-byte loads of one segment (a row of a stored block or of its
+// transpose) for the two rows of a pair: vectors q0 + 64u, u < U, of each
+// row (indices past the segment are clamped to 0; their values are unused).
+template <typename B, int U>
+struct SegRegs {
+    typename Vec16<B>::T t[U], t2[U];
+};
+
+template <typename B, int U>
+__device__ __forceinline__ void seg_load(SegRegs<B, U>& s, const B* rowp, const B* rowp2, int nv, int q0) {
+    using VT = typename Vec16<B>::T;
+    const VT* rv = reinterpret_cast<const VT*>(rowp);
+    const VT* rv2 = reinterpret_cast<const VT*>(rowp2);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int q = q0 + 64 * u < nv ? q0 + 64 * u : 0;
+        s.t[u] = rv[q];
+        s.t2[u] = rv2[q];
+    }
+}
+
+// an entry of v: from LDS when staged, else from global memory (agent-scope
+// coherent when v was written by other workgroups of this launch)
+template <bool COHERENT>
+__device__ __forceinline__ double ldv(const lds_f64* p) { return *p; }
+template <bool COHERENT>
+__device__ __forceinline__ double ldv(const double* p) { return COHERENT ? ld_ag(p) : *p; }
+
+template <typename B, int U, bool COHERENT, typename VP>
+__device__ __forceinline__ void seg_fma(const SegRegs<B, U>& s, int nv, int q0, VP vm, bool want_fro, bool pair,
+                                        double& acc, double& acc2, double& fro) {
+    constexpr int E = Vec16<B>::E;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int q = q0 + 64 * u;
+        if (q < nv) {
+            double e[E], e2[E];
+            Vec16<B>::widen(s.t[u], e);
+            Vec16<B>::widen(s.t2[u], e2);
+#pragma unroll
+            for (int c = 0; c < E; ++c) {
+                const double vj = ldv<COHERENT>(vm + q * E + c);
+                acc = fma(e[c], vj, acc);
+                acc2 = fma(e2[c], vj, acc2);
+                if (want_fro) {
+                    fro = fma(e[c], e[c], fro);
+                    if (pair) fro = fma(e2[c], e2[c], fro);
+                }
+            }
+        }
+    }
+}
+
 // Raw (N-1) J v for the workgroup's own rows, written to out[r]; returns the
 // thread's share of the sum over own rows of ||row||^2 when want_fro.  v is
 // staged in LDS when it fits.  A wave takes two rows of the same mode at a
-// time (rows r and r + waves): both rows' loads of a segment (a row of a
-// stored block or of its transpose) are in flight together and share the
-// reads of v, which halves the memory round trips per row.  Segments are read
-// with 16-byte loads, four per lane and row in flight, when their length and
-// address allow, else element by element.
-template <typename B, bool COHERENT>
-__device__ double matvec_rows(const PostArgs& a, const double* v, double* out, double scale, bool want_fro,
-                              int64_t r_lo, int64_t r_hi, double* vlds) {
-    using VT = typename Vec16<B>::T;
+// time (rows r and r + waves): both rows' loads of a segment are in flight
+// together and share the reads of v.  Segments are read with 16-byte loads,
+// four per lane and row, when their length and address allow, else element
+// by element; two consecutive segments that each fit one round of 16-byte
+// loads have all their loads issued before either is summed, so a row of an
+// order-3 tensor costs one memory round trip.  The summation order is the
+// segments' order either way.
+template <typename B, bool COHERENT, typename VP>
+__device__ __forceinline__ double matvec_rows_v(const PostArgs& a, VP vv, double* out, double scale, bool want_fro, int64_t r_lo,
+                                int64_t r_hi) {
     constexpr int E = Vec16<B>::E;
     constexpr int U = 4;
     constexpr int NWV = BS / 64;
@@ -259,12 +336,6 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
     const B* bt = static_cast<const B*>(a.blocksT);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar table reads
-    const bool staged = a.D <= kVecLds;
-    if (staged) {
-        stage_to_lds<COHERENT>(vlds, v, a.D);
-        __syncthreads();
-    }
-    const double* vv = staged ? vlds : v;
     double fro = 0.0;
     int64_t r = r_lo + wave;
     while (r < r_hi) {
@@ -275,46 +346,49 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
         const bool pair = r2 < r_hi && r2 < a.xoff[n + 1];  // second row of the same mode
         const int64_t i2 = pair ? i + NWV : i;               // (a repeat of row r when unpaired)
         double acc = 0.0, acc2 = 0.0;
-        for (int m = 0; m < a.N; ++m) {
-            if (m == n) continue;
+        // segment m of rows i and i2: the two row pointers, v's part, and
+        // whether it takes one round of 16-byte loads
+        auto seg_rows = [&](int m, const B*& p, const B*& p2) {
             const int len = (int)a.dims[m];
             const B* base = (a.seg_src[n][m] ? bt : blocks) + a.seg_base[n][m];
-            const B* rowp = base + i * (int64_t)len;
-            const B* rowp2 = base + i2 * (int64_t)len;
-            const double* vm = vv + a.xoff[m];
+            p = base + i * (int64_t)len;
+            p2 = base + i2 * (int64_t)len;
+        };
+        auto seg_vec = [&](int m, const B* p) {
             // len % E == 0 makes both rows' offsets multiples of 16 bytes
-            const bool vec = (len % E == 0) && ((reinterpret_cast<uintptr_t>(rowp) & 15) == 0);
+            return ((int)a.dims[m] % E == 0) && ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
+        };
+        int m = n == 0 ? 1 : 0;
+        while (m < a.N) {
+            int mb = m + 1;
+            if (mb == n) ++mb;
+            const int len = (int)a.dims[m];
+            const B *rowp, *rowp2;
+            seg_rows(m, rowp, rowp2);
+            const VP vm = vv + a.xoff[m];
+            const bool vec = seg_vec(m, rowp);
+            const int nv = len / E;
+            if (vec && nv <= 64 * U && mb < a.N) {
+                const int lenb = (int)a.dims[mb];
+                const B *rowpb, *rowp2b;
+                seg_rows(mb, rowpb, rowp2b);
+                const int nvb = lenb / E;
+                if (seg_vec(mb, rowpb) && nvb <= 64 * U) {
+                    SegRegs<B, U> sa, sb;
+                    seg_load<B, U>(sa, rowp, rowp2, nv, lane);
+                    seg_load<B, U>(sb, rowpb, rowp2b, nvb, lane);
+                    seg_fma<B, U, COHERENT>(sa, nv, lane, vm, want_fro, pair, acc, acc2, fro);
+                    seg_fma<B, U, COHERENT>(sb, nvb, lane, vv + a.xoff[mb], want_fro, pair, acc, acc2, fro);
+                    m = mb + 1;
+                    if (m == n) ++m;
+                    continue;
+                }
+            }
             if (vec) {
-                const VT* rv = reinterpret_cast<const VT*>(rowp);
-                const VT* rv2 = reinterpret_cast<const VT*>(rowp2);
-                const int nv = len / E;
                 for (int q0 = lane; q0 < nv; q0 += 64 * U) {
-                    VT t[U], t2[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int q = q0 + 64 * u < nv ? q0 + 64 * u : 0;
-                        t[u] = rv[q];
-                        t2[u] = rv2[q];
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int q = q0 + 64 * u;
-                        if (q < nv) {
-                            double e[E], e2[E];
-                            Vec16<B>::widen(t[u], e);
-                            Vec16<B>::widen(t2[u], e2);
-#pragma unroll
-                            for (int c = 0; c < E; ++c) {
-                                const double vj = (COHERENT && !staged) ? ld_ag(vm + q * E + c) : vm[q * E + c];
-                                acc = fma(e[c], vj, acc);
-                                acc2 = fma(e2[c], vj, acc2);
-                                if (want_fro) {
-                                    fro = fma(e[c], e[c], fro);
-                                    if (pair) fro = fma(e2[c], e2[c], fro);
-                                }
-                            }
-                        }
-                    }
+                    SegRegs<B, U> sa;
+                    seg_load<B, U>(sa, rowp, rowp2, nv, q0);
+                    seg_fma<B, U, COHERENT>(sa, nv, q0, vm, want_fro, pair, acc, acc2, fro);
                 }
             } else {
                 for (int j0 = lane; j0 < len; j0 += 64 * U) {
@@ -330,7 +404,7 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
                         const int j = j0 + 64 * u;
                         if (j < len) {
                             const double e = (double)t[u], e2 = (double)t2[u];
-                            const double vj = (COHERENT && !staged) ? ld_ag(vm + j) : vm[j];
+                            const double vj = ldv<COHERENT>(vm + j);
                             acc = fma(e, vj, acc);
                             acc2 = fma(e2, vj, acc2);
                             if (want_fro) {
@@ -341,6 +415,7 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
                     }
                 }
             }
+            m = mb;
         }
         acc = wave_sum(acc);
         acc2 = wave_sum(acc2);
@@ -353,6 +428,18 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
     return fro;
 }
 
+template <typename B, bool COHERENT>
+__device__ __forceinline__ double matvec_rows(const PostArgs& a, const double* v, double* out, double scale, bool want_fro,
+                              int64_t r_lo, int64_t r_hi, double* vlds) {
+    if (a.D <= kVecLds) {
+        stage_to_lds<COHERENT>(as_lds(vlds), v, a.D);
+        __syncthreads();
+        return matvec_rows_v<B, COHERENT>(a, static_cast<const lds_f64*>(as_lds(vlds)), out, scale, want_fro, r_lo,
+                                          r_hi);
+    }
+    return matvec_rows_v<B, COHERENT>(a, v, out, scale, want_fro, r_lo, r_hi);
+}
+
 // h_i = sum over own rows of V_i[r] w[r] for i <= j into mine[i].  Wave
 // `wave` takes basis vectors i = wave + 4u (u < 8) per round, lanes stride
 // over the own rows; the eight loads per lane are independent.
@@ -362,19 +449,19 @@ __device__ double matvec_rows(const PostArgs& a, const double* v, double* out, d
 constexpr int kVownLds = 8960;  // doubles
 struct OwnV {
     double* V;      // [(kmax+1) * D]
-    double* lds;    // [cap * rows]
+    lds_f64* lds;   // [cap * rows]
     int64_t D, r_lo;
     int rows, cap;
-    __device__ double get(int i, int64_t r) const {
+    __device__ __forceinline__ double get(int i, int64_t r) const {
         return i < cap ? lds[i * rows + (int)(r - r_lo)] : ld_ag(V + (size_t)i * D + r);
     }
-    __device__ void put(int i, int64_t r, double v) const {
+    __device__ __forceinline__ void put(int i, int64_t r, double v) const {
         st_ag(V + (size_t)i * D + r, v);
         if (i < cap) lds[i * rows + (int)(r - r_lo)] = v;
     }
 };
 
-__device__ void own_dots(const OwnV& ov, const double* w, int j, int64_t r_lo, int64_t r_hi, double* mine) {
+__device__ __forceinline__ void own_dots(const OwnV& ov, const double* w, int j, int64_t r_lo, int64_t r_hi, lds_f64* mine) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NW = BS / 64;
@@ -404,8 +491,8 @@ __device__ void own_dots(const OwnV& ov, const double* w, int j, int64_t r_lo, i
 // out[r] = sum_{i<m} c_i V_i[r] over own rows: the four waves take interleaved
 // quarters of i (eight independent loads per lane per round), partial sums
 // meet in LDS in a fixed order.  Returns through `out` (may alias nothing read).
-__device__ void own_combine(const OwnV& ov, int m, int64_t r_lo, int64_t r_hi, const double* c,
-                            double* part /* LDS [NW][64] */, double* out, bool subtract) {
+__device__ __forceinline__ void own_combine(const OwnV& ov, int m, int64_t r_lo, int64_t r_hi, const lds_f64* c,
+                            lds_f64* part /* [NW][64] */, double* out, bool subtract) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NW = BS / 64;
@@ -438,19 +525,19 @@ __device__ void own_combine(const OwnV& ov, int m, int64_t r_lo, int64_t r_hi, c
 // mine[n] = sum over own rows of block n of x[r] w[r]: the components of w
 // along the unit factors, removed by the projection onto the tangent space
 // {v : x_n' v_n = 0 for every n}.
-__device__ void own_xdots(const PostArgs& a, const double* w, int64_t r_lo, int64_t r_hi, double* mine, Lds& L) {
+__device__ __forceinline__ void own_xdots(const PostArgs& a, const double* w, int64_t r_lo, int64_t r_hi, lds_f64* mine, Lds& L) {
     for (int n = 0; n < a.N; ++n) {
         const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
         const int64_t hi = r_hi < L.xoff[n + 1] ? r_hi : L.xoff[n + 1];
         double s = 0.0;
         for (int64_t r = lo + threadIdx.x; r < hi; r += BS) s = fma(a.x[r], w[r], s);
-        s = wg_sum(s, L.red4);
+        s = wg_sum(s, as_lds(L.red4));
         if (threadIdx.x == 0) mine[n] = s;
     }
 }
 
 // w[r] -= c[n] x[r] over own rows of block n (c summed over the grid).
-__device__ void own_xsub(const PostArgs& a, double* w, const double* c, int64_t r_lo, int64_t r_hi, const Lds& L) {
+__device__ __forceinline__ void own_xsub(const PostArgs& a, double* w, const lds_f64* c, int64_t r_lo, int64_t r_hi, const Lds& L) {
     __syncthreads();
     for (int n = 0; n < a.N; ++n) {
         const int64_t lo = r_lo > L.xoff[n] ? r_lo : L.xoff[n];
@@ -474,6 +561,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     int parity = 0;
     if (tid == 0) {
         L.timeout = 0;
+        L.hinted = 0;
         L.epoch0 = __hip_atomic_load(&a.st->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid <= a.N) L.xoff[tid] = a.xoff[tid];
@@ -507,7 +595,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     for (int64_t r = r_lo + tid; r < r_hi && r < L.xoff[1]; r += BS) s0 = fma(a.x[r], a.g[r], s0);
     wg_to_mine(s0, 0, L);
     wg_to_mine(fro, 1, L);
-    allreduce(a, 2, parity, sync, L, vlds);
+    allreduce(a, 2, parity, sync, L, as_lds(vlds));
     HOSCF_MARK(2);
     const double sigma = L.hsum[0];
     const double normJ = sqrt(L.hsum[1]) * inv_n1;
@@ -517,7 +605,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
         rr = fma(e, e, rr);
     }
     wg_to_mine(rr, 0, L);
-    allreduce(a, 1, parity, sync, L, vlds);
+    allreduce(a, 1, parity, sync, L, as_lds(vlds));
     HOSCF_MARK(3);
     const double den = normJ + fabs(sigma);
     const bool zero = !(den > 0.0);  // J = 0: T vanishes on the current factors
@@ -560,7 +648,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     double* V = a.V;
     OwnV ov;
     ov.V = V;
-    ov.lds = vown_lds;
+    ov.lds = as_lds(vown_lds);
     ov.D = D;
     ov.r_lo = r_lo;
     ov.rows = (int)(r_hi - r_lo);
@@ -571,11 +659,11 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     double rb = 0.0;  // adjoint: ||P rhs|| / (N-1), the scale of the Galerkin solution
     if (!done && proj) {
         // V_0 = P rhs / ||P rhs||, with ||P rhs||^2 = ||rhs||^2 - sum_n (x_n' rhs_n)^2
-        own_xdots(a, a.rhs, r_lo, r_hi, L.mine, L);
+        own_xdots(a, a.rhs, r_lo, r_hi, as_lds(L.mine), L);
         double rr2 = 0.0;
         for (int64_t r = r_lo + tid; r < r_hi; r += BS) rr2 = fma(a.rhs[r], a.rhs[r], rr2);
         wg_to_mine(rr2, a.N, L);
-        allreduce(a, a.N + 1, parity, sync, L, vlds);
+        allreduce(a, a.N + 1, parity, sync, L, as_lds(vlds));
         double nb2 = L.hsum[a.N];
         for (int n = 0; n < a.N; ++n) nb2 -= L.hsum[n] * L.hsum[n];
         if (!(nb2 > 0.0)) {
@@ -612,17 +700,17 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             HOSCF_ACC(10);
             // pass 1: h_i = V_i . w over own rows, with ||w||^2 in the same
             // reduction
-            own_dots(ov, w, j, r_lo, r_hi, L.mine);
-            if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 1, L);
+            own_dots(ov, w, j, r_lo, r_hi, as_lds(L.mine));
+            if (proj) own_xdots(a, w, r_lo, r_hi, as_lds(L.mine + j + 1), L);
             {
                 double nn0 = 0.0;
                 for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn0 = fma(w[r], w[r], nn0);
-                nn0 = wg_sum(nn0, L.red4);
+                nn0 = wg_sum(nn0, as_lds(L.red4));
                 if (tid == 0) L.mine[j + 1 + NP] = nn0;
             }
-            allreduce(a, j + 2 + NP, parity, sync, L, vlds);
-            own_combine(ov, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
-            if (proj) own_xsub(a, w, L.hsum + j + 1, r_lo, r_hi, L);
+            allreduce(a, j + 2 + NP, parity, sync, L, as_lds(vlds));
+            own_combine(ov, j + 1, r_lo, r_hi, as_lds(L.hsum), as_lds(L.part), w, true);
+            if (proj) own_xsub(a, w, as_lds(L.hsum + j + 1), r_lo, r_hi, L);
             // The second pass is needed only when the first removed most of w
             // (Kahan / DGKS: the orthogonalised norm, known from Pythagoras,
             // is below 1/sqrt(2) of the original); every workgroup decides
@@ -643,19 +731,19 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                     if (tid == 0) L.al[j] = alpha1;
                     __syncthreads();
                     // pass 2: h'_i and ||w||^2
-                    own_dots(ov, w, j, r_lo, r_hi, L.mine);
+                    own_dots(ov, w, j, r_lo, r_hi, as_lds(L.mine));
                     double nn = 0.0;
                     for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
-                    nn = wg_sum(nn, L.red4);
+                    nn = wg_sum(nn, as_lds(L.red4));
                     if (tid == 0) L.mine[j + 1] = nn;
-                    if (proj) own_xdots(a, w, r_lo, r_hi, L.mine + j + 2, L);
-                    allreduce(a, j + 2 + NP, parity, sync, L, vlds);
+                    if (proj) own_xdots(a, w, r_lo, r_hi, as_lds(L.mine + j + 2), L);
+                    allreduce(a, j + 2 + NP, parity, sync, L, as_lds(vlds));
                     double corr2 = 0.0;
                     for (int i = 0; i <= j; ++i) corr2 = fma(L.hsum[i], L.hsum[i], corr2);
                     for (int i = 0; i < NP; ++i) corr2 = fma(L.hsum[j + 2 + i], L.hsum[j + 2 + i], corr2);
                     beta = sqrt(fmax(L.hsum[j + 1] - corr2, 0.0));
-                    own_combine(ov, j + 1, r_lo, r_hi, L.hsum, L.part, w, true);
-                    if (proj) own_xsub(a, w, L.hsum + j + 2, r_lo, r_hi, L);
+                    own_combine(ov, j + 1, r_lo, r_hi, as_lds(L.hsum), as_lds(L.part), w, true);
+                    if (proj) own_xsub(a, w, as_lds(L.hsum + j + 2), r_lo, r_hi, L);
                     if (tid == 0) L.al[j] += L.hsum[j];
                 }
             }
@@ -679,9 +767,10 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             }
             flag_arrive(a, ++sync);
             // an eigen-step almost never converges in one or two Lanczos steps
-            // (and a Galerkin solve needs two); checks cost a serial
-            // tridiagonal eigensolve, so they start at m = 3
-            const bool check = invariant || m == kmax || (m >= 3 && (m <= 8 || (m % 4) == 0));
+            // (and a Galerkin solve needs two), so checks start at m = 3; from
+            // there every step is checked, so that a run stops at the first
+            // step that meets its tolerance
+            const bool check = invariant || m == kmax || m >= 3;
             if (check) {
                 // every workgroup takes the same decision from the same numbers
                 if (a.mode == kPostEigen) {
@@ -690,25 +779,42 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                         if (m == 1) {
                             lmin = lmax = L.al[0];
                         } else {
-                            extreme_eigs(L.al, L.b2, L.be, m, &lmin, &lmax);
+                            extreme_eigs(L.al, L.b2, L.be, m, &lmin, &lmax, L.hinted != 0, L.hint_lo, L.hint_hi);
                         }
                         if (tid == 0) {
+                            L.hint_lo = lmin;
+                            L.hint_hi = lmax;
+                            L.hinted = 1;
                             const double th = (fabs(lmin) > fabs(lmax) * (1.0 + 1e-12)) ? lmin : lmax;
                             double* sv = L.s;
                             for (int i = 0; i < m; ++i) sv[i] = 1.0;
                             const double zrep = 2.220446049250313e-16 * fmax(fabs(lmin), fabs(lmax)) + 1e-300;
-                            // the shift is accurate to rounding: two inverse iterations suffice
+                            // the shift is accurate to rounding: two inverse iterations suffice,
+                            // both with one factorisation of T_m - theta I.  The second runs
+                            // only when the first leaves the Ritz residual near the tolerance
+                            // (within 16x) or the run ends anyway, so every stop is decided,
+                            // and every Ritz vector used, after two.
+                            double* inv_d = L.tri;
+                            double* du = L.tri + kKmaxLds;
+                            double* du2 = L.tri + 2 * kKmaxLds;
+                            double* fm = L.tri + 3 * kKmaxLds;
+                            tri_factor(L.al, L.be, m, th, zrep, inv_d, du, du2, fm, L.swp);
+                            const double lim = eig_tol * fmax(normJ, fabs(th));
+                            double rz = 0.0;
                             for (int it = 0; it < 2; ++it) {
-                                tri_solve(L.al, L.be, m, th, sv, zrep, L.tri, L.tri + kKmaxLds, L.tri + 2 * kKmaxLds,
-                                          L.tri + 3 * kKmaxLds);
+                                tri_apply(inv_d, du, du2, fm, L.swp, m, sv);
                                 double nrm = 0.0;
+#pragma unroll 8
                                 for (int i = 0; i < m; ++i) nrm = fma(sv[i], sv[i], nrm);
-                                nrm = sqrt(nrm);
-                                for (int i = 0; i < m; ++i) sv[i] /= nrm;
+                                const double inrm = 1.0 / sqrt(nrm);
+#pragma unroll 8
+                                for (int i = 0; i < m; ++i) sv[i] *= inrm;
+                                rz = beta * fabs(sv[m - 1]);
+                                if (it == 0 && rz > 16.0 * lim && !invariant && m != kmax) break;
                             }
                             L.theta = th;
-                            L.ritz = beta * fabs(sv[m - 1]);
-                            L.stop = (L.ritz <= eig_tol * fmax(normJ, fabs(th))) || invariant || m == kmax;
+                            L.ritz = rz;
+                            L.stop = (rz <= lim) || invariant || m == kmax;
                         }
                     }
                 } else if (tid == 0) {
@@ -742,7 +848,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
 
     if (!done && proj) {
         // mu = rb V_m t, t solving (T_m - shift/(N-1)) t = e_1
-        own_combine(ov, m, r_lo, r_hi, L.s, L.part, w, false);
+        own_combine(ov, m, r_lo, r_hi, as_lds(L.s), as_lds(L.part), w, false);
         for (int64_t r = r_lo + tid; r < r_hi; r += BS) a.out[r] = (L.ok ? rb : 0.0) * w[r];
         if (blockIdx.x == 0 && tid == 0) {
             a.st->lanczos = m;
@@ -781,7 +887,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
     if (accept) {
         // y = V_m s (own rows), then per-block norm and largest-|entry|
         const int N = a.N;
-        own_combine(ov, m, r_lo, r_hi, L.s, L.part, w, false);
+        own_combine(ov, m, r_lo, r_hi, as_lds(L.s), as_lds(L.part), w, false);
         __shared__ double wbv[BS / 64], wbs[BS / 64];
         __shared__ int64_t wbi[BS / 64];
         for (int n = 0; n < N; ++n) {
@@ -798,7 +904,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                     bi = r;
                 }
             }
-            const double sn = wg_sum(s2, L.red4);
+            const double sn = wg_sum(s2, as_lds(L.red4));
             for (int k = 32; k >= 1; k >>= 1) {
                 const double ov = __shfl_xor(bv, k);
                 const int64_t oi = __shfl_xor(bi, k);
@@ -854,19 +960,32 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                 stage[idx] = ld_ag(buf + (size_t)wg * a.RK + k);
             }
             __syncthreads();
-            if (tid == 0) {
-                for (int n = 0; n < N; ++n) {
-                    double sn = 0.0, v = -1.0, sg = 0.0, ix = 1e300;
-                    for (int wg = 0; wg < a.nwg; ++wg) {
-                        const double* p = stage + wg * K4 + 4 * n;
-                        const double p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
-                        sn += p0;
-                        if (p1 > v || (p1 == v && p2 < ix)) {
-                            v = p1;
-                            ix = p2;
-                            sg = p3;
-                        }
+            // wave n combines mode n: lanes take workgroups, then a fixed
+            // butterfly sums the norms (a fixed order: deterministic) and picks
+            // the largest |entry|, ties to the lowest index (order-free)
+            const int wv = tid >> 6, ln = tid & 63;
+            for (int n = wv; n < N; n += BS / 64) {
+                double sn = 0.0, v = -1.0, sg = 0.0, ix = 1e300;
+                for (int wg = ln; wg < a.nwg; wg += 64) {
+                    const double* p = stage + wg * K4 + 4 * n;
+                    const double p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
+                    sn += p0;
+                    if (p1 > v || (p1 == v && p2 < ix)) {
+                        v = p1;
+                        ix = p2;
+                        sg = p3;
                     }
+                }
+                for (int o = 32; o >= 1; o >>= 1) {
+                    sn += __shfl_xor(sn, o);
+                    const double ov = __shfl_xor(v, o), oi = __shfl_xor(ix, o), os = __shfl_xor(sg, o);
+                    if (ov > v || (ov == v && oi < ix)) {
+                        v = ov;
+                        ix = oi;
+                        sg = os;
+                    }
+                }
+                if (ln == 0) {
                     L.hsum[2 * n] = sn;
                     L.hsum[2 * n + 1] = sg;
                 }

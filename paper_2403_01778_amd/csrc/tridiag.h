@@ -1,5 +1,6 @@
 // Device helpers for the symmetric tridiagonal matrices of Lanczos runs:
-// Sturm counts, extreme eigenvalues by multisection, and a pivoted solve.
+// Sturm counts, extreme eigenvalues by multisection, a pivoted solve, and a
+// pivoted factorisation kept for repeated solves.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,8 +28,16 @@ __device__ inline int sturm_count(const double* al, const double* b2, int m, dou
     double d = al[0] - x;
     if (fabs(d) < pivmin) d = -pivmin;
     cnt += d < 0.0;
+    // the next step's entries are read one step ahead, so the LDS latency
+    // overlaps the pivot recurrence instead of adding to it
+    double an = m > 1 ? al[1] : 0.0, bn = m > 1 ? b2[0] : 0.0;
     for (int k = 1; k < m; ++k) {
-        d = (al[k] - x) - fast_div(b2[k - 1], d);
+        const double ak = an, bk = bn;
+        if (k + 1 < m) {
+            an = al[k + 1];
+            bn = b2[k];
+        }
+        d = (ak - x) - fast_div(bk, d);
         if (fabs(d) < pivmin) d = -pivmin;
         cnt += d < 0.0;
     }
@@ -36,55 +45,91 @@ __device__ inline int sturm_count(const double* al, const double* b2, int m, dou
 }
 
 // Extreme eigenvalues of T_m by 32-way multisection per end (wave 0 only;
-// lanes 0-31 bracket the smallest, lanes 32-63 the largest).
+// lanes 0-31 bracket the smallest, lanes 32-63 the largest).  Every round
+// evaluates one Sturm count per lane at increasing points of each bracket;
+// the first point with enough eigenvalues below it closes the new bracket.
+//
+// Warm start (`warm`): lo_hint and hi_hint are the extreme eigenvalues of a
+// leading principal submatrix T_k, k < m (an earlier check of the same
+// Lanczos run).  By Cauchy interlacing the smallest eigenvalue of T_m lies
+// below lo_hint and the largest above hi_hint, so each bracket starts at
+// its hint; and as the Ritz values converge they move little between
+// checks.  The first round therefore places its points at geometrically
+// growing distances from the hint (from the final tolerance up to the
+// Gershgorin bound), which brackets the new value within a width of the
+// order of its move; the uniform rounds then start from that bracket.
 __device__ inline void extreme_eigs(const double* al, const double* b2, const double* be, int m, double* out_lo,
-                             double* out_hi) {
+                                    double* out_hi, bool warm = false, double lo_hint = 0.0, double hi_hint = 0.0) {
     const int lane = threadIdx.x & 63;
+    // Gershgorin bounds and the largest b^2, rows strided over the lanes
     double glo = 1e300, ghi = -1e300, bmax = 0.0;
-    for (int k = 0; k < m; ++k) {
+    for (int k = lane; k < m; k += 64) {
         const double r = (k > 0 ? fabs(be[k - 1]) : 0.0) + (k < m - 1 ? fabs(be[k]) : 0.0);
         glo = fmin(glo, al[k] - r);
         ghi = fmax(ghi, al[k] + r);
         if (k < m - 1) bmax = fmax(bmax, b2[k]);
     }
+    for (int o = 32; o >= 1; o >>= 1) {
+        glo = fmin(glo, __shfl_xor(glo, o));
+        ghi = fmax(ghi, __shfl_xor(ghi, o));
+        bmax = fmax(bmax, __shfl_xor(bmax, o));
+    }
     const double scale = fmax(fabs(glo), fabs(ghi));
     const double pivmin = 1e-290 * fmax(1.0, bmax);
     const double pad = 2.0 * 2.220446049250313e-16 * scale + pivmin;
-    double lo0 = glo - pad, hi0 = ghi + pad;  // interval for the smallest eigenvalue
-    double lo1 = glo - pad, hi1 = ghi + pad;  // interval for the largest
+    const double tol = 4.0 * 2.220446049250313e-16 * scale + pivmin;
+    double lo0 = glo - pad, hi0 = ghi + pad;  // bracket of the smallest
+    double lo1 = glo - pad, hi1 = ghi + pad;  // bracket of the largest
     const bool low_half = lane < 32;
     const int sub = lane & 31;
-    for (int round = 0; round < 14; ++round) {
-        const double lo = low_half ? lo0 : lo1, hi = low_half ? hi0 : hi1;
-        const double x = lo + (hi - lo) * (double)(sub + 1) / 33.0;
+    bool geometric = false;
+    if (warm) {
+        // the hints are midpoints of brackets of width <= tol
+        hi0 = fmin(hi0, lo_hint + tol);
+        lo1 = fmax(lo1, hi_hint - tol);
+        geometric = hi0 > lo0 && hi1 > lo1;
+        if (!geometric) {
+            hi0 = ghi + pad;
+            lo1 = glo - pad;
+        }
+    }
+    for (int round = 0; round < 15; ++round) {
+        double x;
+        if (geometric && round == 0) {
+            // distances tol * r^e, e = 0..31, with tol * r^32 = the bracket's width
+            const double span = low_half ? hi0 - lo0 : hi1 - lo1;
+            const double lr = log(fmax(span / tol, 1.0)) * (1.0 / 32.0);
+            const double dist = tol * exp(lr * (double)(low_half ? 31 - sub : sub));
+            x = low_half ? hi0 - dist : lo1 + dist;
+        } else {
+            const double lo = low_half ? lo0 : lo1, hi = low_half ? hi0 : hi1;
+            x = lo + (hi - lo) * (double)(sub + 1) / 33.0;
+        }
         const int c = sturm_count(al, b2, m, x, pivmin);
         // smallest: first point with count >= 1; largest: first point with count == m
         const bool hit = low_half ? (c >= 1) : (c >= m);
         const unsigned long long bal = __ballot(hit);
         const unsigned lo_bits = (unsigned)(bal & 0xffffffffull);
         const unsigned hi_bits = (unsigned)(bal >> 32);
-        // lane-uniform update of both intervals
-        const double xs_lo_step = (hi0 - lo0) / 33.0;
-        const double xs_hi_step = (hi1 - lo1) / 33.0;
+        // lane-uniform update of both brackets from the points of the lanes
         if (lo_bits) {
             const int f = __ffs(lo_bits) - 1;
-            const double nhi = lo0 + xs_lo_step * (f + 1);
-            const double nlo = f > 0 ? lo0 + xs_lo_step * f : lo0;
+            const double nhi = __shfl(x, f);
+            const double nlo = f > 0 ? __shfl(x, f - 1) : lo0;
             lo0 = nlo;
             hi0 = nhi;
         } else {
-            lo0 = lo0 + xs_lo_step * 32;
+            lo0 = __shfl(x, 31);
         }
         if (hi_bits) {
             const int f = __ffs(hi_bits) - 1;
-            const double nhi = lo1 + xs_hi_step * (f + 1);
-            const double nlo = f > 0 ? lo1 + xs_hi_step * f : lo1;
+            const double nhi = __shfl(x, 32 + f);
+            const double nlo = f > 0 ? __shfl(x, 31 + f) : lo1;
             lo1 = nlo;
             hi1 = nhi;
         } else {
-            lo1 = lo1 + xs_hi_step * 32;
+            lo1 = __shfl(x, 63);
         }
-        const double tol = 4.0 * 2.220446049250313e-16 * scale + pivmin;
         if (hi0 - lo0 <= tol && hi1 - lo1 <= tol) break;
     }
     *out_lo = 0.5 * (lo0 + hi0);
@@ -136,6 +181,133 @@ __device__ inline bool tri_solve(const double* al, const double* be, int m, doub
     if (m >= 2) y[m - 2] = (y[m - 2] - du[m - 2] * y[m - 1]) / d[m - 2];
     for (int i = m - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / d[i];
     return true;
+}
+
+// LU factorisation with partial pivoting of T_m - shift I, kept for several
+// solves (single thread): the multipliers in fm, the row swaps as bits of
+// swp, and U as its inverted diagonal inv_d and two superdiagonals du, du2.
+// The elimination is the one tri_solve performs; the pivot and the current
+// superdiagonal entry are carried in registers, so each step waits on
+// arithmetic only, and the next row's entries are read one step ahead.
+// Zero pivots are replaced by `zrep` when zrep > 0; otherwise the call
+// reports singularity (returns false).
+__device__ inline bool tri_factor(const double* al, const double* be, int m, double shift, double zrep, double* inv_d,
+                                  double* du, double* du2, double* fm, uint64_t* swp) {
+    for (int w = 0; w * 64 < m; ++w) swp[w] = 0;
+    double di = al[0] - shift;              // pivot candidate of row i
+    double ui = m > 1 ? be[0] : 0.0;        // row i's entry right of the diagonal
+    double an = m > 1 ? al[1] : 0.0;        // next row's diagonal (unshifted)
+    double bn = m > 2 ? be[1] : 0.0;        // next row's superdiagonal
+    double sub = ui;                        // row i+1's entry left of the diagonal (symmetric)
+    uint64_t bits = 0;
+    for (int i = 0; i < m - 1; ++i) {
+        const double dnext = an - shift, unext = bn;
+        if (i + 2 < m) {
+            an = al[i + 2];
+            bn = i + 2 < m - 1 ? be[i + 2] : 0.0;
+        }
+        if (fabs(di) >= fabs(sub)) {
+            if (di == 0.0) {
+                if (zrep <= 0.0) return false;
+                di = zrep;
+            }
+            const double r = 1.0 / di;
+            const double f = sub * r;
+            fm[i] = f;
+            inv_d[i] = r;
+            du[i] = ui;
+            du2[i] = 0.0;
+            di = fma(-f, ui, dnext);
+            ui = unext;
+        } else {
+            const double f = di / sub;
+            fm[i] = f;
+            bits |= 1ull << (i & 63);
+            inv_d[i] = 1.0 / sub;
+            du[i] = dnext;
+            du2[i] = i < m - 2 ? unext : 0.0;
+            di = fma(-f, dnext, ui);
+            ui = -f * unext;
+        }
+        sub = unext;  // be[i+1], the next step's subdiagonal entry
+        if ((i & 63) == 63) {
+            swp[i >> 6] = bits;
+            bits = 0;
+        }
+    }
+    if (((m - 1) & 63) != 0) swp[(m - 1) >> 6] = bits;
+    if (di == 0.0) {
+        if (zrep <= 0.0) return false;
+        di = zrep;
+    }
+    inv_d[m - 1] = 1.0 / di;
+    return true;
+}
+
+// y := (T_m - shift I)^{-1} y with a factorisation from tri_factor (single
+// thread).  Both recurrences carry their latest entries in registers and
+// read the operands of four steps at once, so that one LDS round trip serves
+// four dependent steps.
+__device__ inline void tri_apply(const double* inv_d, const double* du, const double* du2, const double* fm,
+                                 const uint64_t* swp, int m, double* y) {
+    // forward: the row swaps and multipliers of the elimination; a swap at
+    // step i exchanges y[i] and y[i+1] before the update
+    double yi = y[0];
+    int i = 0;
+    for (; i + 4 <= m - 1; i += 4) {
+        double f[4], yn[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            f[u] = fm[i + u];
+            yn[u] = y[i + 1 + u];
+        }
+        const unsigned bits = (unsigned)(swp[i >> 6] >> (i & 63));  // i % 4 == 0: one word holds all four
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool sw = (bits >> u) & 1u;
+            const double keep = sw ? yn[u] : yi, other = sw ? yi : yn[u];
+            y[i + u] = keep;
+            yi = fma(-f[u], keep, other);
+        }
+    }
+    for (; i < m - 1; ++i) {
+        const double f = fm[i], yn = y[i + 1];
+        const bool sw = (swp[i >> 6] >> (i & 63)) & 1ull;
+        const double keep = sw ? yn : yi, other = sw ? yi : yn;
+        y[i] = keep;
+        yi = fma(-f, keep, other);
+    }
+    // back substitution, U upper triangular with two superdiagonals
+    double y1 = yi * inv_d[m - 1];  // y[i+1]
+    y[m - 1] = y1;
+    if (m < 2) return;
+    double y2 = y1;                 // y[i+2] (unused when i = m-2)
+    y1 = (y[m - 2] - du[m - 2] * y1) * inv_d[m - 2];
+    y[m - 2] = y1;
+    i = m - 3;
+    for (; i >= 3; i -= 4) {
+        double yv[4], a1[4], a2[4], id[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            yv[u] = y[i - u];
+            a1[u] = du[i - u];
+            a2[u] = du2[i - u];
+            id[u] = inv_d[i - u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double yi0 = (yv[u] - a1[u] * y1 - a2[u] * y2) * id[u];
+            y[i - u] = yi0;
+            y2 = y1;
+            y1 = yi0;
+        }
+    }
+    for (; i >= 0; --i) {
+        const double yi0 = (y[i] - du[i] * y1 - du2[i] * y2) * inv_d[i];
+        y[i] = yi0;
+        y2 = y1;
+        y1 = yi0;
+    }
 }
 
 }  // namespace hoscf
