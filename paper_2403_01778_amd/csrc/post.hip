@@ -417,12 +417,13 @@ __device__ __forceinline__ double matvec_rows_v(const PostArgs& a, VP vv, double
             }
             m = mb;
         }
-        acc = wave_sum(acc);
-        acc2 = wave_sum(acc2);
-        if (lane == 0) {
-            out[r] = acc * scale;
-            if (pair) out[r2] = acc2 * scale;
-        }
+        // both rows' sums in one transposed butterfly: lane 0 ends with row
+        // r's total, lane 32 with row r2's
+        double t2[2] = {acc, acc2};
+        int base = 0;
+        xred64<2, 6>(t2, lane, base);
+        if (lane == 0) out[r] = t2[0] * scale;
+        if (lane == 32 && pair) out[r2] = t2[0] * scale;
         r += pair ? 2 * NWV : NWV;
     }
     return fro;
@@ -479,11 +480,13 @@ __device__ __forceinline__ void own_dots(const OwnV& ov, const double* w, int j,
                 h[u] = fma(i <= j ? vi : 0.0, wr, h[u]);
             }
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double t = wave_sum(h[u]);
-            const int i = i0 + u * NW;
-            if (lane == 0 && i <= j) mine[i] = t;
+        // the eight sums in one transposed butterfly: lanes 8b..8b+7 end
+        // with the total of h[b]
+        int base = 0;
+        xred64<8, 6>(h, lane, base);
+        {
+            const int i = i0 + base * NW;
+            if ((lane & 7) == 0 && i <= j) mine[i] = h[0];
         }
     }
 }
