@@ -462,11 +462,14 @@ struct OwnV {
     }
 };
 
-__device__ __forceinline__ void own_dots(const OwnV& ov, const double* w, int j, int64_t r_lo, int64_t r_hi, lds_f64* mine) {
+// Index j + 1 stands for w itself: its sum, ||w||^2 over own rows, goes to
+// mine[norm_slot].
+__device__ __forceinline__ void own_dots(const OwnV& ov, const double* w, int j, int64_t r_lo, int64_t r_hi,
+                                         lds_f64* mine, int norm_slot) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NW = BS / 64;
-    for (int i0 = wave; i0 <= j; i0 += 8 * NW) {
+    for (int i0 = wave; i0 <= j + 1; i0 += 8 * NW) {
         double h[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) h[u] = 0.0;
@@ -476,17 +479,19 @@ __device__ __forceinline__ void own_dots(const OwnV& ov, const double* w, int j,
             for (int u = 0; u < 8; ++u) {
                 const int i = i0 + u * NW;
                 const int ic = i <= j ? i : 0;
-                const double vi = ov.get(ic, r);
-                h[u] = fma(i <= j ? vi : 0.0, wr, h[u]);
+                const double vg = ov.get(ic, r);
+                const double vi = i <= j ? vg : (i == j + 1 ? wr : 0.0);
+                h[u] = fma(vi, wr, h[u]);
             }
         }
         // the eight sums in one transposed butterfly: lanes 8b..8b+7 end
         // with the total of h[b]
         int base = 0;
         xred64<8, 6>(h, lane, base);
-        {
+        if ((lane & 7) == 0) {
             const int i = i0 + base * NW;
-            if ((lane & 7) == 0 && i <= j) mine[i] = h[0];
+            if (i <= j) mine[i] = h[0];
+            else if (i == j + 1) mine[norm_slot] = h[0];
         }
     }
 }
@@ -703,14 +708,8 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
             HOSCF_ACC(10);
             // pass 1: h_i = V_i . w over own rows, with ||w||^2 in the same
             // reduction
-            own_dots(ov, w, j, r_lo, r_hi, as_lds(L.mine));
+            own_dots(ov, w, j, r_lo, r_hi, as_lds(L.mine), j + 1 + NP);
             if (proj) own_xdots(a, w, r_lo, r_hi, as_lds(L.mine + j + 1), L);
-            {
-                double nn0 = 0.0;
-                for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn0 = fma(w[r], w[r], nn0);
-                nn0 = wg_sum(nn0, as_lds(L.red4));
-                if (tid == 0) L.mine[j + 1 + NP] = nn0;
-            }
             allreduce(a, j + 2 + NP, parity, sync, L, as_lds(vlds));
             own_combine(ov, j + 1, r_lo, r_hi, as_lds(L.hsum), as_lds(L.part), w, true);
             if (proj) own_xsub(a, w, as_lds(L.hsum + j + 1), r_lo, r_hi, L);
@@ -734,11 +733,7 @@ __global__ __launch_bounds__(BS) void post_kernel(PostArgs a) {
                     if (tid == 0) L.al[j] = alpha1;
                     __syncthreads();
                     // pass 2: h'_i and ||w||^2
-                    own_dots(ov, w, j, r_lo, r_hi, as_lds(L.mine));
-                    double nn = 0.0;
-                    for (int64_t r = r_lo + tid; r < r_hi; r += BS) nn = fma(w[r], w[r], nn);
-                    nn = wg_sum(nn, as_lds(L.red4));
-                    if (tid == 0) L.mine[j + 1] = nn;
+                    own_dots(ov, w, j, r_lo, r_hi, as_lds(L.mine), j + 1);
                     if (proj) own_xdots(a, w, r_lo, r_hi, as_lds(L.mine + j + 2), L);
                     allreduce(a, j + 2 + NP, parity, sync, L, as_lds(vlds));
                     double corr2 = 0.0;
