@@ -78,6 +78,7 @@ struct BatchLds {
     double xi[16];         // mode-1 entries x_{s,1}[i] of the previous terms at the current slab
     double sc[8];
     double theta;
+    uint64_t swp[(kBatchKmax + 63) / 64]; // row swaps of the tridiagonal factorisation
     int item, stop, ok;
 };
 
@@ -348,7 +349,11 @@ __device__ int batch_lanczos(BatchLds& L, const int* I, int D, double* V, int mo
         __syncthreads();
         m = j + 1;
         const bool invariant = beta <= 1e-14 * normJ;
-        if (invariant || m == kBatchKmax || (m >= 3 && (m <= 8 || (m % 4) == 0))) {
+        // checked at every step from m = 3 (the check factorises once and
+        // usually runs one inverse iteration, so it costs less than a step it
+        // could save; the warm-started multisection of the post kernel would
+        // push this kernel past its registers)
+        if (invariant || m == kBatchKmax || m >= 3) {
             if (mode == 0) {
                 if (tid < 64) {
                     double lmin = L.al[0], lmax = L.al[0];
@@ -357,17 +362,26 @@ __device__ int batch_lanczos(BatchLds& L, const int* I, int D, double* V, int mo
                         const double th = (fabs(lmin) > fabs(lmax) * (1.0 + 1e-12)) ? lmin : lmax;
                         for (int i = 0; i < m; ++i) L.s[i] = 1.0;
                         const double zrep = 2.220446049250313e-16 * fmax(fabs(lmin), fabs(lmax)) + 1e-300;
+                        // two inverse iterations with one factorisation of T_m - theta I;
+                        // the second only near the tolerance (within 16x) or at the end
+                        double* inv_d = L.tri;
+                        double* du = L.tri + kBatchKmax;
+                        double* du2 = L.tri + 2 * kBatchKmax;
+                        double* fm = L.tri + 3 * kBatchKmax;
+                        tri_factor(L.al, L.be, m, th, zrep, inv_d, du, du2, fm, L.swp);
+                        const double lim = tol * fmax(normJ, fabs(th));
+                        double ritz = 0.0;
                         for (int rep = 0; rep < 2; ++rep) {
-                            tri_solve(L.al, L.be, m, th, L.s, zrep, L.tri, L.tri + kBatchKmax,
-                                      L.tri + 2 * kBatchKmax, L.tri + 3 * kBatchKmax);
+                            tri_apply<1>(inv_d, du, du2, fm, L.swp, m, L.s);
                             double nrm = 0.0;
                             for (int i = 0; i < m; ++i) nrm = fma(L.s[i], L.s[i], nrm);
-                            nrm = sqrt(nrm);
-                            for (int i = 0; i < m; ++i) L.s[i] /= nrm;
+                            const double inrm = 1.0 / sqrt(nrm);
+                            for (int i = 0; i < m; ++i) L.s[i] *= inrm;
+                            ritz = beta * fabs(L.s[m - 1]);
+                            if (rep == 0 && ritz > 16.0 * lim && !invariant && m != kBatchKmax) break;
                         }
                         L.theta = th;
-                        const double ritz = beta * fabs(L.s[m - 1]);
-                        L.stop = (ritz <= tol * fmax(normJ, fabs(th))) || invariant || m == kBatchKmax;
+                        L.stop = (ritz <= lim) || invariant || m == kBatchKmax;
                     }
                 }
             } else if (tid == 0) {

@@ -245,16 +245,19 @@ __device__ inline bool tri_factor(const double* al, const double* be, int m, dou
 }
 
 // y := (T_m - shift I)^{-1} y with a factorisation from tri_factor (single
-// thread).  Both recurrences carry their latest entries in registers and
-// read the operands of four steps at once, so that one LDS round trip serves
-// four dependent steps.
+// thread).  Both recurrences carry their latest entries in registers and,
+// with UNROLL = 4, read the operands of four steps at once, so that one LDS
+// round trip serves four dependent steps (UNROLL = 1 keeps register use low
+// for kernels that have none to spare).
+template <int UNROLL = 4>
 __device__ inline void tri_apply(const double* inv_d, const double* du, const double* du2, const double* fm,
                                  const uint64_t* swp, int m, double* y) {
+    static_assert(UNROLL == 1 || UNROLL == 4, "tri_apply: unroll by 1 or 4");
     // forward: the row swaps and multipliers of the elimination; a swap at
     // step i exchanges y[i] and y[i+1] before the update
     double yi = y[0];
     int i = 0;
-    for (; i + 4 <= m - 1; i += 4) {
+    for (; UNROLL == 4 && i + 4 <= m - 1; i += 4) {
         double f[4], yn[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -285,7 +288,7 @@ __device__ inline void tri_apply(const double* inv_d, const double* du, const do
     y1 = (y[m - 2] - du[m - 2] * y1) * inv_d[m - 2];
     y[m - 2] = y1;
     i = m - 3;
-    for (; i >= 3; i -= 4) {
+    for (; UNROLL == 4 && i >= 3; i -= 4) {
         double yv[4], a1[4], a2[4], id[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
