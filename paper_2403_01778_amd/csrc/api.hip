@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -15,6 +16,35 @@
 using namespace hoscf;
 
 namespace {
+
+// Pinned host copies of the solve state for the iteration loop's status
+// fetch, reused across calls: allocated on first use and kept until the
+// process ends (a hipHostMalloc / hipHostFree pair per call costs more than
+// an iteration of a small solve).  Calls on several threads take separate
+// buffers.
+std::mutex g_pinned_mu;
+std::vector<SolveState*> g_pinned_free;
+
+SolveState* pinned_acquire() {
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        if (!g_pinned_free.empty()) {
+            SolveState* p = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return p;
+        }
+    }
+    SolveState* p = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(SolveState), hipHostMallocDefault) != hipSuccess)
+        return nullptr;
+    return p;
+}
+
+void pinned_release(SolveState* p) {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned_free.push_back(p);
+}
+
 
 __global__ void init_state_kernel(SolveState* st) {
     if (threadIdx.x == 0) {
@@ -242,8 +272,8 @@ int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* op
     const int64_t D = lay.sweep.map.D;
     const unsigned cgrid = (unsigned)std::min<int64_t>((D + 255) / 256, 1024);
 
-    SolveState* h = nullptr;
-    HOSCF_TRY(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(SolveState), hipHostMallocDefault));
+    SolveState* h = pinned_acquire();
+    if (!h) return HOSCF_HIP_ERROR;
     hoscf_info info{};
     int status = HOSCF_NOT_CONVERGED;
     auto fetch = [&]() -> hipError_t {
@@ -346,7 +376,7 @@ int hoscf_solve(const hoscf_tensor* T, const double* x0, const hoscf_options* op
     info.status = status;
     if (sigma_host) *sigma_host = info.lambda;
     if (info_host) *info_host = info;
-    hipHostFree(h);
+    pinned_release(h);
     return status;
 }
 

@@ -17,6 +17,8 @@
 // without partial sums.  Inner products are combined across workgroups in a
 // fixed order, so the result does not depend on timing.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "common.h"
 #include "post.h"
@@ -1117,14 +1119,26 @@ hipError_t PostPlan::run(int mode, const void* blocks, const void* blocksT, doub
     return hipLaunchCooperativeKernel(fn, dim3(a.nwg), dim3(BS), params, 0, s);
 }
 
+// Resident workgroup capacity of the post kernel, cached per device and
+// block type (the occupancy query is not free and plans are built per call).
 int post_max_workgroups(bool f64) {
+    static std::mutex mu;
+    static std::map<std::pair<int, bool>, int> cache;
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = cache.find({dev, f64});
+        if (it != cache.end()) return it->second;
+    }
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
     const void* fn = f64 ? reinterpret_cast<const void*>(&post_kernel<double>)
                          : reinterpret_cast<const void*>(&post_kernel<float>);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, BS, 0) != hipSuccess) return 1;
-    return std::max(1, cus * std::max(per, 1));
+    const int n = std::max(1, cus * std::max(per, 1));
+    std::lock_guard<std::mutex> lk(mu);
+    cache[{dev, f64}] = n;
+    return n;
 }
 
 }  // namespace hoscf
