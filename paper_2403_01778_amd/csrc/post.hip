@@ -37,7 +37,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum over the workgroup (256 threads); every thread receives the total.
+// Sum over the workgroup (BS threads); every thread receives the total.
 __device__ __forceinline__ double wg_sum(double v, lds_f64* lds_w) {
     v = wave_sum(v);
     __syncthreads();
@@ -498,9 +498,9 @@ __device__ __forceinline__ void own_dots(const OwnV& ov, const double* w, int j,
     }
 }
 
-// out[r] = sum_{i<m} c_i V_i[r] over own rows: the four waves take interleaved
-// quarters of i (eight independent loads per lane per round), partial sums
-// meet in LDS in a fixed order.  Returns through `out` (may alias nothing read).
+// out[r] = sum_{i<m} c_i V_i[r] over own rows: the waves take interleaved
+// groups of eight i (eight independent loads per lane per round), partial
+// sums meet in LDS in a fixed order.  Returns through `out` (may alias nothing read).
 __device__ __forceinline__ void own_combine(const OwnV& ov, int m, int64_t r_lo, int64_t r_hi, const lds_f64* c,
                             lds_f64* part /* [NW][64] */, double* out, bool subtract) {
     const int lane = threadIdx.x & 63;
